@@ -1,0 +1,117 @@
+"""Pins of the embedding, max-statistic and greedy oracle (CPU only)."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle.ksg import ksg_cmi
+from oracle.stats import (embed, greedy_select, max_statistic, omnibus_test,
+                          order_statistic_threshold)
+
+
+def test_embed_hand_example():
+    # 2 trials, 2 vars, T = 5, max_lag 2 -> t = 2, 3, 4 in each trial
+    data = np.arange(20, dtype=np.float32).reshape(2, 2, 5)
+    cand, y = embed(data, target=1, max_lag=2)
+    # var 0 lag 1: trial 0 -> x0(1..3) = 1,2,3 ; trial 1 -> 11,12,13
+    assert cand[0].tolist() == [1, 2, 3, 11, 12, 13]
+    # var 0 lag 2: 0,1,2 ; 10,11,12
+    assert cand[1].tolist() == [0, 1, 2, 10, 11, 12]
+    # var 1 lag 1: 6,7,8 ; 16,17,18
+    assert cand[2].tolist() == [6, 7, 8, 16, 17, 18]
+    assert cand[3].tolist() == [5, 6, 7, 15, 16, 17]
+    assert y.tolist() == [7, 8, 9, 17, 18, 19]
+
+
+def test_max_statistic_hand_example():
+    # 3 candidates, 4 rounds; candidate 1 and 2 tie on the original -> lowest index (1)
+    t = np.array([[0.10, 0.05, 0.30, 0.01, 0.02],
+                  [0.50, 0.20, 0.10, 0.60, 0.00],
+                  [0.50, 0.40, 0.00, 0.00, 0.00]])
+    ms = max_statistic(t, alpha=0.5)
+    assert ms.c_star == 1 and ms.t_obs == 0.5
+    assert ms.t_max.tolist() == [0.40, 0.30, 0.60, 0.02]
+    assert ms.count == 1 and ms.pval == 0.25 and ms.significant
+    assert not max_statistic(t, alpha=0.25).significant  # p < alpha is strict
+
+
+def test_single_candidate_is_plain_permutation_test():
+    g = workloads.rng(4)
+    for _ in range(50):
+        P = int(g.integers(5, 300))
+        row = g.standard_normal(P + 1)
+        ms = max_statistic(row[None, :], alpha=0.05)
+        assert ms.c_star == 0
+        assert ms.count == int(np.sum(row[1:] >= row[0]))
+        assert ms.pval == np.mean(row[1:] >= row[0])
+
+
+def test_order_statistic_identity():
+    g = workloads.rng(5)
+    for trial in range(400):
+        P = int(g.choice([20, 100, 200, 500]))
+        c = int(g.integers(1, 8))
+        t = np.round(g.standard_normal((c, P + 1)), 1)  # coarse values: many ties
+        for alpha in (0.05, 0.01):
+            ms = max_statistic(t, alpha)
+            tau = order_statistic_threshold(ms.t_max, alpha)
+            assert ms.significant == (ms.t_obs > tau), (trial, alpha)
+
+
+def test_pvalue_uniform_under_null():
+    # exchangeable originals and surrogates -> the p-value is (discretely) uniform
+    from scipy import stats
+    g = workloads.rng(6)
+    ps = []
+    for _ in range(2000):
+        t = g.standard_normal((5, 101))
+        ps.append(max_statistic(t).pval)
+    assert stats.kstest(ps, "uniform").pvalue > 1e-3
+    assert abs(np.mean(np.array(ps) < 0.05) - 0.05) < 0.02
+
+
+def _chain(seed, n=400):
+    """y(t) driven by x1(t-1) only; x0 and x2 independent noise (3 vars, lag 1..2)."""
+    g = workloads.rng(seed)
+    T = n + 2
+    x = g.standard_normal((3, T))
+    x[1] = g.standard_normal(T)
+    yv = np.zeros(T)
+    yv[1:] = 0.9 * x[1, :-1] + 0.3 * g.standard_normal(T - 1)
+    data = np.stack([x[0], x[1], x[2], yv])[None].astype(np.float32)
+    return data
+
+
+def test_greedy_recovers_single_driver():
+    data = _chain(11)
+    cand, y = embed(data, target=3, max_lag=2)
+    perms = workloads.permutations(y.size, 39, seed=12)
+    sel, steps = greedy_select(cand, y, 4, perms, alpha=0.05)
+    assert sel[0] == 1 * 2 + 0  # var 1, lag 1
+    assert steps[0].significant and steps[0].count == 0
+    assert not steps[-1].significant  # stops on a non-significant step
+    assert len(sel) == len(steps) - 1
+
+
+def test_greedy_step_table_consistency():
+    data = _chain(13, n=200)
+    cand, y = embed(data, target=3, max_lag=2)
+    perms = workloads.permutations(y.size, 19, seed=14)
+    sel, steps, tables = greedy_select(cand, y, 4, perms, return_cmis=True, max_steps=2)
+    # row 0 of the first table is the plain CMI of candidate 0 given nothing
+    assert tables[0][0, 0] == ksg_cmi(cand[0], y, None, 4)
+    assert tables[0][0, 3] == ksg_cmi(cand[0][perms[2]], y, None, 4)
+    if len(sel) >= 1 and len(tables) > 1:
+        z = cand[sel[0]][:, None]
+        pool = [c for c in range(cand.shape[0]) if c != sel[0]]
+        assert tables[1][0, 0] == ksg_cmi(cand[pool[0]], y, z, 4)
+
+
+def test_omnibus():
+    data = _chain(15, n=300)
+    cand, y = embed(data, target=3, max_lag=2)
+    perms = workloads.permutations(y.size, 19, seed=16)
+    sel = [2, 6]  # var1 lag1 (source) and target lag 1
+    tab, ms = omnibus_test(cand, y, sel, target=3, max_lag=2, k=4, perms=perms)
+    assert tab[0, 0] == ksg_cmi(cand[2], y, cand[6], 4)
+    assert ms.significant
+    assert omnibus_test(cand, y, [6], 3, 2, 4, perms) is None
