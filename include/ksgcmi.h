@@ -1,0 +1,311 @@
+/*
+ * ksgcmi.h - C ABI of the MI355X (gfx950) nearest-neighbour conditional mutual
+ * information library.
+ *
+ * What is computed.  The paper (IDTxl, Summary) describes greedy multivariate
+ * transfer-entropy network inference: for every target a parent set is built by
+ * repeatedly adding the candidate past variable that maximises a conditional
+ * mutual information (CMI) criterion, each inclusion gated by a test against
+ * null distributions from surrogate data (network-inference paragraph), with the
+ * nonlinear KSG nearest-neighbour estimator (Kraskov, Stoegbauer & Grassberger
+ * 2004) as the accurate continuous estimator and direct estimator access for
+ * (conditional) MI (estimator paragraph).  The paper prints no formula; the
+ * estimator is KSG algorithm 1 in the CMI form of Frenzel & Pompe (2007):
+ *
+ *   d_ij^S  = max over the coordinates a of subspace S of |fl32(p_ja - p_ia)|
+ *   eps_i   = k-th smallest of { d_ij^XYZ : j != i }          (multiset order statistic)
+ *   n_S(i)  = #{ j != i : d_ij^S < eps_i },  S in {XZ, YZ, Z}  (strict; d^Z = 0 if Z empty)
+ *   I       = psi(k) - <psi(n_XZ+1) + psi(n_YZ+1) - psi(n_Z+1)>
+ *           = H_{k-1} - (1/N) sum_i [H_{n_XZ(i)} + H_{n_YZ(i)} - H_{n_Z(i)}]   (nats)
+ *
+ * with every coordinate difference one IEEE FP32 round-to-nearest-even
+ * subtraction and FP64 harmonic numbers H_n.  Results are not clipped at 0.
+ *
+ * Conventions.
+ *  - Every function returns a ksg_status; nothing throws or aborts across the ABI.
+ *  - Pointers are DEVICE pointers unless a comment says "host".  The caller owns
+ *    every buffer it passes; the library never frees or retains caller memory
+ *    beyond the call (device work is stream-ordered on the context's stream).
+ *  - Point sets are structure-of-arrays: a d-dimensional variable of N points is
+ *    d columns of N floats, column c at ptr[c*N + i].
+ *  - Arguments are validated on the host before any device work.  Non-finite
+ *    data are rejected with KSG_ENONFINITE by a device-side check (one stream
+ *    synchronisation) unless KSG_OPT_CHECK_FINITE is switched off.
+ *  - A context is not thread-safe: use one context per host thread.  Contexts on
+ *    one device share nothing.
+ *  - ksg_last_error(ctx) describes the last failure on that context.
+ *
+ * Limits: 1 <= k <= 16, N > k, N <= 2^31 - 1024, d_x >= 1, d_y >= 1, d_z >= 0,
+ * d_x + d_y + d_z <= 16.
+ */
+#ifndef KSGCMI_H
+#define KSGCMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ksg_status {
+  KSG_OK = 0,
+  KSG_EINVAL = 1,      /* bad argument (null pointer, dims, k, sizes, options) */
+  KSG_ETOOFEW = 2,     /* N <= k: the k-th neighbour does not exist */
+  KSG_ENONFINITE = 3,  /* NaN or infinity in the input data */
+  KSG_ENOMEM = 4,      /* device or pinned-host allocation failed */
+  KSG_EDEVICE = 5,     /* a HIP runtime call failed (message in ksg_last_error) */
+  KSG_ENODEV = 6,      /* no usable HIP device */
+  KSG_EBUFSMALL = 7    /* caller-provided output capacity too small (needed size reported) */
+} ksg_status;
+
+#define KSG_MAX_DIMS 16
+#define KSG_MAX_K 16
+
+typedef struct ksg_ctx ksg_ctx;
+
+/* Library version as 10000*major + 100*minor + patch. */
+int ksg_version(void);
+
+/* Human-readable name of a status code (static string). */
+const char* ksg_status_string(int status);
+
+/* Number of visible HIP devices (0 when none); never fails. */
+int ksg_device_count(void);
+
+/* Host utility (no device needed): harmonic numbers H_0..H_nmax (H_n = sum_{m<=n} 1/m, so
+ * psi(n+1) = H_n - Euler's gamma) into the host array out[nmax+1], FP64, from a
+ * double-double running sum.  These are the digamma values the estimator uses.
+ * Errors: KSG_EINVAL (nmax < 0, out NULL). */
+int ksg_harmonic_table(int64_t nmax, double* out);
+
+/* Create a context on HIP device `device`, issuing all work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the context.
+ * Errors: KSG_EINVAL (out == NULL, device out of range), KSG_ENODEV. */
+int ksg_ctx_create(ksg_ctx** out, int device, void* hip_stream);
+
+/* Release a context and its workspace (waits for its pending work). NULL is a no-op. */
+void ksg_ctx_destroy(ksg_ctx* ctx);
+
+/* Text of the last error on this context; valid until the next call on it. */
+const char* ksg_last_error(const ksg_ctx* ctx);
+
+/* Options. */
+typedef enum ksg_option {
+  KSG_OPT_CHECK_FINITE = 1, /* 1 (default): reject non-finite data; 0: trust inputs */
+  KSG_OPT_TILE_VARIANT = 2, /* -1 (default): autotuned tile variant; >= 0 forces one */
+  KSG_OPT_USE_GRAPH = 3,    /* 1 (default): replay greedy steps from a captured hipGraph */
+  KSG_OPT_TIMING = 4        /* 1: time every search-kernel launch with HIP events (default 0) */
+} ksg_option;
+int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
+
+/* With KSG_OPT_TIMING on: device time of the search kernels (search + count + per-tile
+ * digamma sums, finalisation excluded) summed over all launches since the last call, in
+ * milliseconds, with their launch count and algorithmic operation count
+ * (sum over problems of N(N-1)(4D+2), the brute-force FP32 op count: per ordered pair D
+ * subtractions, D-1 maxima and 1 compare for the radius, the same plus 3 compares for the
+ * counts).  Synchronises the stream; resets the accumulators.  Outputs are host pointers. */
+int ksg_take_timing(ksg_ctx* ctx, double* ms, int64_t* launches, double* ops);
+
+/* ---------------------------------------------------------------------------
+ * Single estimate (direct estimator access, Summary estimator paragraph).
+ * x, y, z: SoA columns, dims[0], dims[1], dims[2] columns of N floats (z may be
+ * NULL iff dims[2] == 0).  k: neighbour rank.  *out_nats (host): the estimate.
+ * Synchronises the context's stream.
+ * Errors: KSG_EINVAL, KSG_ETOOFEW, KSG_ENONFINITE, KSG_ENOMEM, KSG_EDEVICE. */
+int cmi_ksg(ksg_ctx* ctx, const float* x, const float* y, const float* z, int64_t N,
+            const int32_t dims[3], int32_t k, double* out_nats);
+
+/* ---------------------------------------------------------------------------
+ * Batched estimates: every problem of the batch runs in one persistent launch
+ * (work items = (problem, 256-query tile), longest first).
+ *
+ * perm_x: NULL, or an int32 row gather of length n applied to X only
+ * (X'[i] = X[perm_x[i]]: a permutation surrogate, Summary network-inference
+ * paragraph); Y and Z are never permuted.
+ * eps_out / counts_out / local_out: NULL or per-point outputs: eps_i (FP32 [n]),
+ * counts (int32 [3][n]: n_XZ, n_YZ, n_Z) and the local (pointwise) CMI values
+ * psi(k) - psi(n_XZ+1) - psi(n_YZ+1) + psi(n_Z+1) (FP64 [n]).
+ */
+typedef struct ksg_problem {
+  int64_t n;
+  int32_t dx, dy, dz, k;
+  const float* x;
+  const float* y;
+  const float* z;
+  const int32_t* perm_x;
+  float* eps_out;
+  int32_t* counts_out;
+  double* local_out;
+} ksg_problem;
+
+/* probs: host array of n_probs problems.  out_nats: device FP64 [n_probs].
+ * Stream-ordered: returns once the work is queued (after the optional finite
+ * check, which synchronises).  Inputs must stay valid until the stream reaches
+ * the end of the batch.
+ * Errors: KSG_EINVAL (with the index of the first bad problem in ksg_last_error),
+ * KSG_ETOOFEW, KSG_ENONFINITE, KSG_ENOMEM, KSG_EDEVICE. */
+int cmi_ksg_batch(ksg_ctx* ctx, const ksg_problem* probs, int32_t n_probs, double* out_nats);
+
+/* ---------------------------------------------------------------------------
+ * Max-statistic surrogate test (Summary, network-inference paragraph: surrogate
+ * null distributions gate each inclusion; problem paragraph: errors from testing
+ * many sources are controlled).  cmi: device FP64 [c][P+1]; column 0 holds the
+ * c original estimates, columns 1..P the surrogate rounds (round p applies the
+ * same permutation to every candidate).
+ *   c_star = argmax_c cmi[c][0] (lowest index wins ties), t_obs = cmi[c_star][0]
+ *   T_p    = max_c cmi[c][p],  count = #{p : T_p >= t_obs},  pval = count / P
+ *   significant = pval < alpha;  tau05 / tau01 = ceil(0.05 P)-th / ceil(0.01 P)-th
+ *   largest T_p (so that p < alpha  <=>  t_obs > tau_alpha).
+ * out: host.  Synchronises.  Errors: KSG_EINVAL, KSG_EDEVICE. */
+typedef struct ksg_maxstat_result {
+  int32_t c_star;
+  int32_t count;
+  int32_t significant;
+  int32_t n_perm;
+  double t_obs;
+  double pval;
+  double tau05;
+  double tau01;
+} ksg_maxstat_result;
+int ksg_maxstat(ksg_ctx* ctx, const double* cmi, int32_t c, int32_t n_perm, double alpha,
+                ksg_maxstat_result* out);
+
+/* ---------------------------------------------------------------------------
+ * Lagged embedding (Summary, network-inference paragraph: the conditioning
+ * builds a non-uniform embedding of candidate past variables and optimises
+ * source-target delays).  data: device FP32 [n_trials][n_vars][T] (the generic
+ * multivariate time-series format, Summary last paragraph).  Embedded points are
+ * t = max_lag .. T-1 of every trial, pooled trial-major: N = n_trials*(T-max_lag).
+ * cand_out: device FP32 [n_vars*max_lag][N]; candidate v*max_lag + (l-1) holds
+ * x_v(t - l).  y_out: device FP32 [N], x_target(t).  Stream-ordered.
+ * Errors: KSG_EINVAL. */
+int ksg_embed(ksg_ctx* ctx, const float* data, int32_t n_vars, int64_t T, int32_t n_trials,
+              int32_t target, int32_t max_lag, float* cand_out, float* y_out);
+
+/* ---------------------------------------------------------------------------
+ * One greedy step on embedded columns (the unit that select_parents repeats): for
+ * every candidate c in pool and every round p = 0..n_perm (0 = original data,
+ * p >= 1 = X rows gathered through perms[p-1], the same gather for every candidate)
+ * estimate I(X_c ; Y | Z) with Z = the cond columns, all in one batched launch, then
+ * apply the max-statistic test.
+ * cand: device FP32 [C][N] columns (layout of ksg_embed); y: device FP32 [N];
+ * pool, cond: host int32 candidate indices (< C, not checked against C: the caller
+ * guarantees they address columns of cand); perms: device int32 [n_perm][N];
+ * cmi_out: device FP64 [n_pool][n_perm+1]; result: host.  Synchronises.
+ * Errors: KSG_EINVAL, KSG_ETOOFEW, KSG_ENONFINITE, KSG_ENOMEM, KSG_EDEVICE. */
+int ksg_greedy_step(ksg_ctx* ctx, const float* cand, const float* y, int64_t N, const int32_t* pool,
+                    int32_t n_pool, const int32_t* cond, int32_t n_cond, const int32_t* perms,
+                    int32_t n_perm, int32_t k, double alpha, double* cmi_out,
+                    ksg_maxstat_result* result);
+
+/* ---------------------------------------------------------------------------
+ * Greedy parent selection for one target (Summary, network-inference paragraph).
+ * Candidates: every variable's past (the target's own included) at lags
+ * 1..max_lag, index v*max_lag + (lag-1), one pool.  Each step estimates the CMI
+ * of every remaining candidate and its n_perm surrogates given the selected set
+ * in one batched launch, applies the max-statistic test and either includes the
+ * argmax (significant) or stops.  perms: device int32 [n_perm][N] row
+ * permutations, N = n_trials*(T-max_lag); surrogate round p uses perms[p-1] for
+ * every candidate.  With omnibus = 1 the final source set is tested jointly:
+ * I(selected sources ; Y | selected target past), surrogates permuting the
+ * source block rows.
+ *
+ * Learned null: learned != NULL gates each step first with the threshold
+ * network (ksg_mlp) evaluated on the step's feature vector; only steps whose
+ * t_obs lies within [tau05_hat - margin_lo*s, tau05_hat + margin_hi*s],
+ * s = |tau01_hat - tau05_hat|, run the surrogates.  judge = 1 also runs the
+ * plain test on every step, uses ITS decision, and counts disagreements.
+ */
+typedef struct ksg_mlp ksg_mlp;
+
+typedef struct ksg_select_opts {
+  int32_t k;
+  int32_t max_lag;
+  int32_t n_perm;
+  int32_t omnibus;
+  double alpha;
+  const int32_t* perms;
+  const ksg_mlp* learned;
+  double margin_lo;
+  double margin_hi;
+  int32_t judge;
+  int32_t max_steps; /* 0 = until the test stops or the pool is empty */
+} ksg_select_opts;
+
+/* Per-step record (host arrays of `capacity` entries, caller-allocated; any may be NULL). */
+typedef struct ksg_parent_set {
+  int32_t capacity;
+  int32_t n;            /* parents selected (inclusion order) */
+  int32_t* var;         /* [capacity] variable of each parent */
+  int32_t* lag;         /* [capacity] lag of each parent */
+  double* cmi;          /* [capacity] t_obs of the step that included it */
+  double* pval;         /* [capacity] its p-value (-1 when decided by the learned gate) */
+  int32_t n_steps;      /* tests run, including the final non-significant one */
+  int32_t n_fallback;   /* learned path: steps that ran the full surrogate test */
+  int32_t n_disagree;   /* judge mode: steps where gate and plain test disagreed */
+  int32_t n_gate_decided; /* learned path: steps decided by the gate alone */
+  int32_t omnibus_tested;
+  int32_t omnibus_significant;
+  double omnibus_cmi;
+  double omnibus_pval;
+  int64_t n_cmi;        /* CMI estimates computed (originals + surrogates) */
+} ksg_parent_set;
+
+/* data: device FP32 [n_trials][n_vars][T].  out: host struct.
+ * Errors: KSG_EINVAL, KSG_ETOOFEW, KSG_ENONFINITE, KSG_ENOMEM, KSG_EDEVICE,
+ * KSG_EBUFSMALL (more parents than capacity; out->n holds the number needed). */
+int select_parents(ksg_ctx* ctx, const float* data, int32_t n_vars, int64_t T, int32_t n_trials,
+                   int32_t target, const ksg_select_opts* opts, ksg_parent_set* out);
+
+/* ---------------------------------------------------------------------------
+ * Learned null: a 16-64-64-2 perceptron (ReLU hidden layers, BF16 parameters,
+ * FP32 accumulation) predicting the step's tau_0.05 and tau_0.01 thresholds
+ * scaled by sqrt(N).  The paper has no learned null; this is the build's gate
+ * in front of the surrogate test of the network-inference paragraph, which stays
+ * as the fallback and the judge.
+ *
+ * Parameter layout (5378 floats): W1[64][16] b1[64] W2[64][64] b2[64] W3[2][64] b3[2].
+ * Features (16 per step, raw, standardised inside the network with mu/sd):
+ *   log N, d_x, d_y, d_z, k, log c, log P, sqrt(N)*(largest, second largest,
+ *   mean, sd of the c original CMIs), skewness and excess kurtosis of Y, mean
+ *   skewness, mean excess kurtosis and mean |lag-1 autocorrelation| of the
+ *   candidate columns.
+ */
+#define KSG_MLP_NPARAMS 5378
+#define KSG_MLP_NFEAT 16
+
+/* init: host FP32 [5378] initial master parameters.  */
+int ksg_mlp_create(ksg_ctx* ctx, ksg_mlp** out, const float* init);
+void ksg_mlp_destroy(ksg_mlp* m);
+/* mu, sd: host FP32 [16] feature standardisation (sd > 0). */
+int ksg_mlp_set_norm(ksg_mlp* m, const float* mu, const float* sd);
+/* Copy FP32 master parameters to host [5378] (bf16 = 1: the BF16-rounded values in use). */
+int ksg_mlp_get_params(const ksg_mlp* m, float* out, int32_t bf16);
+int ksg_mlp_set_params(ksg_mlp* m, const float* params);
+/* Forward: feats device FP32 [B][16] raw features -> out device FP32 [B][2]. */
+int ksg_mlp_forward(ksg_ctx* ctx, const ksg_mlp* m, const float* feats, int64_t B, float* out);
+/* Loss and gradient of L = (1/B) sum_b 0.5 |out_b - t_b|^2 with respect to the
+ * BF16 parameters: grad device FP32 [5378], loss device FP32 [1]. */
+int ksg_mlp_grad(ksg_ctx* ctx, const ksg_mlp* m, const float* feats, const float* targets,
+                 int64_t B, float* grad, float* loss);
+/* Adam training (beta1 0.9, beta2 0.999, eps 1e-8) on device data, minibatches of
+ * `batch` rows taken in order; loss_hist (host [epochs] or NULL) gets the mean
+ * minibatch loss of every epoch. */
+int ksg_mlp_train(ksg_ctx* ctx, ksg_mlp* m, const float* feats, const float* targets, int64_t B,
+                  int32_t epochs, int32_t batch, float lr, float* loss_hist);
+int ksg_mlp_save(const ksg_mlp* m, const char* path);
+int ksg_mlp_load(ksg_ctx* ctx, ksg_mlp** out, const char* path);
+
+/* Step features on the device: orig_cmi device FP64 [c]; y device FP32 [N];
+ * cand device FP32 columns, cand_idx host int32 [c] (which candidate columns of
+ * the pool are in the step); out device FP32 [16].  Used by select_parents; exposed
+ * for parity tests. */
+int ksg_step_features(ksg_ctx* ctx, const double* orig_cmi, int32_t c, const float* y,
+                      const float* cand, int64_t N, const int32_t* cand_idx, int32_t dx,
+                      int32_t dy, int32_t dz, int32_t k, int32_t n_perm, float* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KSGCMI_H */

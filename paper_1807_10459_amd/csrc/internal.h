@@ -1,0 +1,94 @@
+// Internal data structures shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ksg {
+
+constexpr int kMaxDims = 16;
+constexpr int kTileQ = 256;       // queries per work item (4 waves x 64 lanes, one query per lane)
+constexpr int kPad = 64;          // column length is padded to a multiple of this with +inf
+constexpr int kMaxK = 16;
+
+// One CMI problem as the search kernel sees it.  Columns are ordered X..., Y..., Z...,
+// each padded with +inf rows up to n_pad.  128 + 64 bytes, 16-byte aligned.
+struct alignas(16) ProbDesc {
+  const float* col[kMaxDims];
+  int32_t n;          // points
+  int32_t n_pad;      // multiple of kPad
+  int32_t dx, dy, dz, k;
+  int32_t n_tiles;    // ceil(n / kTileQ)
+  int32_t part_base;  // first slot of this problem's per-tile partial sums
+  float* eps_out;     // optional per-point outputs (nullptr when not wanted)
+  int32_t* counts_out;
+  double* local_out;
+  int32_t variant;    // shape id (see shape_id)
+  int32_t out_index;  // slot in the output array
+  int32_t swap_xy;    // 1: X and Y were exchanged to reach a fast shape (count rows swap back)
+  int32_t pad_[3];
+};
+
+// Work item: one query tile of one problem.
+struct WorkItem {
+  int32_t prob;
+  int32_t tile;
+};
+
+// A column copy job for the pack kernel: dst[i] = src[perm ? perm[i] : i] (i < n),
+// +inf for n <= i < n_pad.
+struct PackJob {
+  const float* src;
+  const int32_t* perm;
+  float* dst;
+  int32_t n;
+  int32_t n_pad;
+};
+
+// Fast shapes are (dx, dy) in {(1,1), (1,2), (2,2)} with dz in [0, kFastMaxDz]; every
+// other shape uses the generic path.  dx > dy is canonicalised by swapping X and Y
+// (the estimator is symmetric in X and Y, bit for bit).
+constexpr int kFastMaxDz = 12;
+constexpr int kGenericShape = 1000;
+
+inline int shape_id(int dx, int dy, int dz) {
+  int pair = -1;
+  if (dx == 1 && dy == 1) pair = 0;
+  else if (dx == 1 && dy == 2) pair = 1;
+  else if (dx == 2 && dy == 2) pair = 2;
+  if (pair < 0 || dz > kFastMaxDz || dx + dy + dz > kMaxDims) return kGenericShape;
+  return pair * (kFastMaxDz + 1) + dz;
+}
+
+// Step-level outputs of the max-statistic kernel (mirrors ksg_maxstat_result).
+struct MaxStatOut {
+  int32_t c_star;
+  int32_t count;
+  int32_t significant;
+  int32_t n_perm;
+  double t_obs;
+  double pval;
+  double tau05;
+  double tau01;
+};
+
+// ---- launchers implemented in the .hip translation units ----
+// Search + count + per-tile digamma partial sums for every work item, then the
+// per-problem finalisation.  kp = number of top-k registers (5, 9 or 17).
+hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
+                             int* d_counter, const double* d_htab, double* d_partials, int shape,
+                             int kp, int grid, hipStream_t stream);
+hipError_t launch_finalize(const ProbDesc* d_desc, int n_probs, const double* d_partials,
+                           const double* d_htab, double* d_out, int* d_counter, hipStream_t stream);
+int ksg_batch_grid(int shape, int kp, int device_cus);
+
+hipError_t launch_pack(const PackJob* d_jobs, int n_jobs, int max_pad, int* d_flag, hipStream_t stream);
+hipError_t launch_finite_check(const PackJob* d_jobs, int n_jobs, int max_pad, int* d_flag,
+                               hipStream_t stream);
+hipError_t launch_embed(const float* data, int n_vars, int64_t T, int n_trials, int target,
+                        int max_lag, float* cand, float* y, int64_t col_stride,
+                        hipStream_t stream);
+hipError_t launch_maxstat(const double* cmi, int c, int n_perm, double alpha, MaxStatOut* out,
+                          hipStream_t stream);
+
+}  // namespace ksg

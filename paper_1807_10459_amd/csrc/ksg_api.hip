@@ -1,0 +1,590 @@
+// Host runtime behind the C ABI: context, workspace, harmonic-number table, work queue,
+// batched launches, max-statistic test and the greedy parent-selection driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/ksgcmi.h"
+#include "internal.h"
+#include "runtime.h"
+
+using namespace ksg;
+
+// ============================================================== errors
+
+int ksg_ctx::fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  err = buf;
+  return status;
+}
+
+int ksg_ctx::hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? KSG_ENOMEM : KSG_EDEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+#define KSG_HIP(ctx, expr)                                 \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #expr); \
+  } while (0)
+
+// ============================================================== device buffers
+
+int ksg_ctx::reserve(DevBuf& b, size_t bytes, const char* what) {
+  if (b.cap >= bytes) return KSG_OK;
+  // Pending work may still read the old buffer.
+  KSG_HIP(this, hipStreamSynchronize(stream));
+  if (b.ptr) {
+    KSG_HIP(this, hipFree(b.ptr));
+    b.ptr = nullptr;
+    b.cap = 0;
+  }
+  size_t want = std::max(bytes, b.cap + b.cap / 2);
+  want = (want + 4095) & ~size_t(4095);
+  hipError_t e = hipMalloc(&b.ptr, want);
+  if (e != hipSuccess) {
+    want = (bytes + 4095) & ~size_t(4095);
+    (void)hipGetLastError();
+    e = hipMalloc(&b.ptr, want);
+  }
+  if (e != hipSuccess) {
+    b.ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(KSG_ENOMEM, "cannot allocate %zu bytes for %s", bytes, what);
+  }
+  b.cap = want;
+  return KSG_OK;
+}
+
+int ksg_ctx::reserve_host(size_t bytes) {
+  if (staging_cap >= bytes) return wait_staging();
+  int st = wait_staging();
+  if (st) return st;
+  if (staging) KSG_HIP(this, hipHostFree(staging));
+  staging = nullptr;
+  size_t want = std::max(bytes, staging_cap * 2);
+  want = (want + 4095) & ~size_t(4095);
+  hipError_t e = hipHostMalloc(&staging, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    staging = nullptr;
+    staging_cap = 0;
+    (void)hipGetLastError();
+    return fail(KSG_ENOMEM, "cannot allocate %zu bytes of pinned host memory", want);
+  }
+  staging_cap = want;
+  return KSG_OK;
+}
+
+int ksg_ctx::wait_staging() {
+  if (staging_pending) {
+    KSG_HIP(this, hipEventSynchronize(staging_done));
+    staging_pending = false;
+  }
+  return KSG_OK;
+}
+
+// Harmonic numbers H_0..H_nmax in FP64 from a double-double running sum of 1/m (the
+// remainder of each reciprocal comes from an exact fused multiply-add), rounded once.
+void ksg_build_harmonic(int64_t nmax, double* out) {
+  double hi = 0.0, lo = 0.0;
+  out[0] = 0.0;
+  for (int64_t m = 1; m <= nmax; ++m) {
+    const double dm = (double)m;
+    const double r = 1.0 / dm;
+    const double e = std::fma(-r, dm, 1.0) / dm;  // 1/m = r + e (to ~2^-106 relative)
+    // (hi, lo) += (r, e): two-sum of the leading parts, then renormalise.
+    const double s = hi + r;
+    const double bb = s - hi;
+    const double err = (hi - (s - bb)) + (r - bb);
+    const double t = err + lo + e;
+    hi = s + t;
+    lo = t - (hi - s);
+    out[m] = hi;
+  }
+}
+
+int ksg_ctx::ensure_htab(int64_t n) {
+  if (htab_n >= n) return KSG_OK;
+  int64_t want = std::max<int64_t>(std::max<int64_t>(n, 2 * htab_n), 65536);
+  std::vector<double> h(want + 1);
+  ksg_build_harmonic(want, h.data());
+  int st = reserve(htab, sizeof(double) * (want + 1), "harmonic table");
+  if (st) return st;
+  KSG_HIP(this, hipMemcpy(htab.ptr, h.data(), sizeof(double) * (want + 1), hipMemcpyHostToDevice));
+  htab_n = want;
+  return KSG_OK;
+}
+
+// ============================================================== context
+
+extern "C" int ksg_version(void) { return 10000; }
+
+extern "C" const char* ksg_status_string(int s) {
+  switch (s) {
+    case KSG_OK: return "ok";
+    case KSG_EINVAL: return "invalid argument";
+    case KSG_ETOOFEW: return "too few points (N <= k)";
+    case KSG_ENONFINITE: return "non-finite input data";
+    case KSG_ENOMEM: return "out of memory";
+    case KSG_EDEVICE: return "HIP runtime error";
+    case KSG_ENODEV: return "no HIP device";
+    case KSG_EBUFSMALL: return "output buffer too small";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int ksg_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
+}
+
+extern "C" int ksg_harmonic_table(int64_t nmax, double* out) {
+  if (nmax < 0 || !out) return KSG_EINVAL;
+  ksg_build_harmonic(nmax, out);
+  return KSG_OK;
+}
+
+extern "C" int ksg_ctx_create(ksg_ctx** out, int device, void* hip_stream) {
+  if (!out) return KSG_EINVAL;
+  *out = nullptr;
+  const int nd = ksg_device_count();
+  if (nd <= 0) return KSG_ENODEV;
+  if (device < 0 || device >= nd) return KSG_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) {
+    (void)hipGetLastError();
+    return KSG_ENODEV;
+  }
+  ksg_ctx* c = new ksg_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return KSG_EDEVICE;
+  }
+  c->cus = prop.multiProcessorCount;
+  std::snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+  if (hipMalloc(&c->d_counter, sizeof(int) * 4) != hipSuccess ||
+      hipMemset(c->d_counter, 0, sizeof(int) * 4) != hipSuccess ||
+      hipMalloc(&c->d_ms, sizeof(MaxStatOut) * 2) != hipSuccess ||
+      hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(&c->h_ms, sizeof(MaxStatOut) * 2, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    ksg_ctx_destroy(c);
+    return KSG_ENOMEM;
+  }
+  c->d_flag = c->d_counter + 1;
+  *out = c;
+  return KSG_OK;
+}
+
+extern "C" void ksg_ctx_destroy(ksg_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (DevBuf* b : {&c->htab, &c->pool, &c->desc, &c->items, &c->partials, &c->jobs, &c->tmp,
+                    &c->embed, &c->cmi, &c->aux, &c->feat})
+    if (b->ptr) (void)hipFree(b->ptr);
+  if (c->d_counter) (void)hipFree(c->d_counter);
+  if (c->d_ms) (void)hipFree(c->d_ms);
+  if (c->h_ms) (void)hipHostFree(c->h_ms);
+  if (c->staging) (void)hipHostFree(c->staging);
+  if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+  for (auto& pr : c->timed) c->event_pool.insert(c->event_pool.end(), {pr.first, pr.second});
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  (void)hipGetLastError();
+  delete c;
+}
+
+extern "C" const char* ksg_last_error(const ksg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int ksg_ctx_set_option(ksg_ctx* c, int option, int64_t value) {
+  if (!c) return KSG_EINVAL;
+  switch (option) {
+    case KSG_OPT_CHECK_FINITE: c->check_finite = value != 0; return KSG_OK;
+    case KSG_OPT_TILE_VARIANT: c->tile_variant = (int)value; return KSG_OK;
+    case KSG_OPT_USE_GRAPH: c->use_graph = value != 0; return KSG_OK;
+    case KSG_OPT_TIMING: c->timing = value != 0; return KSG_OK;
+    default: return c->fail(KSG_EINVAL, "unknown option %d", option);
+  }
+}
+
+// ============================================================== batch engine
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int ksg_ctx::validate(const Problem& p, int index) {
+  const int D = p.dx + p.dy + p.dz;
+  if (p.dx < 1 || p.dy < 1 || p.dz < 0 || D > KSG_MAX_DIMS)
+    return fail(KSG_EINVAL, "problem %d: dims (%d,%d,%d) outside d_x>=1, d_y>=1, d_z>=0, sum<=%d",
+                index, p.dx, p.dy, p.dz, KSG_MAX_DIMS);
+  if (p.k < 1 || p.k > KSG_MAX_K)
+    return fail(KSG_EINVAL, "problem %d: k=%d outside [1, %d]", index, p.k, KSG_MAX_K);
+  if (p.n > (int64_t)INT32_MAX - 1024)
+    return fail(KSG_EINVAL, "problem %d: N=%lld too large", index, (long long)p.n);
+  if (p.n <= p.k)
+    return fail(KSG_ETOOFEW, "problem %d: N=%lld <= k=%d", index, (long long)p.n, p.k);
+  for (int a = 0; a < D; ++a)
+    if (!p.col[a]) return fail(KSG_EINVAL, "problem %d: null column %d", index, a);
+  return KSG_OK;
+}
+
+int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
+  const int np = (int)probs.size();
+  if (np == 0) return KSG_OK;
+  int64_t nmax = 0;
+  for (int i = 0; i < np; ++i) {
+    int st = validate(probs[i], i);
+    if (st) return st;
+    nmax = std::max<int64_t>(nmax, probs[i].n);
+  }
+  int st = ensure_htab(nmax);
+  if (st) return st;
+
+  // ---- column pool: pack every column that is not already a padded device column ----
+  struct Key {
+    const float* src;
+    const int32_t* perm;
+    int64_t n;
+    bool operator==(const Key& o) const { return src == o.src && perm == o.perm && n == o.n; }
+  };
+  struct KeyHash {
+    size_t operator()(const Key& k) const {
+      return std::hash<const void*>()(k.src) * 31u ^ std::hash<const void*>()(k.perm) ^ (size_t)k.n;
+    }
+  };
+  std::unordered_map<Key, int64_t, KeyHash> slot;
+  std::vector<PackJob> jobs;
+  int64_t pool_floats = 0;
+  int max_pad = 0;
+  // First pass: assign pool offsets (as integers; converted to pointers once the pool exists).
+  std::vector<std::array<int64_t, kMaxDims>> col_off(np);
+  for (int i = 0; i < np; ++i) {
+    const Problem& p = probs[i];
+    const int D = p.dx + p.dy + p.dz;
+    const int64_t n_pad = round_up(p.n, kPad);
+    max_pad = std::max<int>(max_pad, (int)n_pad);
+    for (int a = 0; a < D; ++a) {
+      if (p.padded[a] && !p.perm[a]) {
+        col_off[i][a] = -1;  // used in place
+        continue;
+      }
+      Key key{p.col[a], p.perm[a], p.n};
+      auto it = slot.find(key);
+      if (it == slot.end()) {
+        it = slot.emplace(key, pool_floats).first;
+        PackJob j;
+        j.src = p.col[a];
+        j.perm = p.perm[a];
+        j.dst = reinterpret_cast<float*>(pool_floats);  // offset for now
+        j.n = (int)p.n;
+        j.n_pad = (int)n_pad;
+        jobs.push_back(j);
+        pool_floats += n_pad;
+      }
+      col_off[i][a] = it->second;
+    }
+  }
+  st = reserve(pool, sizeof(float) * std::max<int64_t>(pool_floats, 1), "column pool");
+  if (st) return st;
+  float* pool_base = static_cast<float*>(pool.ptr);
+  for (PackJob& j : jobs) j.dst = pool_base + reinterpret_cast<int64_t>(j.dst);
+
+  // ---- descriptors (longest-processing-time first) and work items ----
+  std::vector<int> order(np);
+  for (int i = 0; i < np; ++i) order[i] = i;
+  auto cost = [&](int i) {
+    const Problem& p = probs[i];
+    return (double)p.n * (double)p.n * (4.0 * (p.dx + p.dy + p.dz) + 2.0);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::vector<ProbDesc> descs(np);
+  std::vector<WorkItem> items;
+  int part = 0;
+  int common_shape = -2;
+  int kp = 5;
+  for (int i = 0; i < np; ++i) {
+    const Problem& p = probs[i];
+    kp = std::max(kp, p.k + 1 <= 5 ? 5 : (p.k + 1 <= 9 ? 9 : 17));
+  }
+  for (int r = 0; r < np; ++r) {
+    const int i = order[r];
+    const Problem& p = probs[i];
+    ProbDesc& d = descs[r];
+    std::memset(&d, 0, sizeof d);
+    const bool swap = p.dx > p.dy;
+    const int dx = swap ? p.dy : p.dx, dy = swap ? p.dx : p.dy;
+    const int D = p.dx + p.dy + p.dz;
+    // source dimension for each canonical slot
+    for (int a = 0; a < D; ++a) {
+      int src = a;
+      if (swap) {
+        if (a < dx) src = p.dx + a;            // canonical X = original Y
+        else if (a < dx + dy) src = a - dx;    // canonical Y = original X
+      }
+      d.col[a] = col_off[i][src] < 0 ? p.col[src] : pool_base + col_off[i][src];
+    }
+    d.n = (int)p.n;
+    d.n_pad = (int)round_up(p.n, kPad);
+    d.dx = dx;
+    d.dy = dy;
+    d.dz = p.dz;
+    d.k = p.k;
+    d.n_tiles = (int)((p.n + kTileQ - 1) / kTileQ);
+    d.part_base = part;
+    d.eps_out = p.eps_out;
+    d.counts_out = p.counts_out;
+    d.local_out = p.local_out;
+    d.variant = shape_id(dx, dy, p.dz);
+    d.out_index = p.out_index;
+    d.swap_xy = swap ? 1 : 0;
+    for (int t = 0; t < d.n_tiles; ++t) items.push_back(WorkItem{r, t});
+    part += d.n_tiles;
+    if (common_shape == -2) common_shape = d.variant;
+    else if (common_shape != d.variant) common_shape = -1;
+  }
+  if (common_shape >= kGenericShape) common_shape = -1;
+
+  // ---- upload: one pinned staging block, one copy ----
+  const size_t sz_desc = sizeof(ProbDesc) * np;
+  const size_t sz_items = sizeof(WorkItem) * items.size();
+  const size_t sz_jobs = sizeof(PackJob) * jobs.size();
+  st = reserve_host(sz_desc + sz_items + sz_jobs + 64);
+  if (st) return st;
+  st = reserve(desc, sz_desc, "descriptors");
+  if (!st) st = reserve(this->items, sz_items, "work items");
+  if (!st) st = reserve(this->jobs, std::max<size_t>(sz_jobs, 16), "pack jobs");
+  if (!st) st = reserve(partials, sizeof(double) * std::max(part, 1), "partial sums");
+  if (st) return st;
+  char* h = static_cast<char*>(staging);
+  std::memcpy(h, descs.data(), sz_desc);
+  std::memcpy(h + sz_desc, items.data(), sz_items);
+  if (sz_jobs) std::memcpy(h + sz_desc + sz_items, jobs.data(), sz_jobs);
+  KSG_HIP(this, hipMemcpyAsync(desc.ptr, h, sz_desc, hipMemcpyHostToDevice, stream));
+  KSG_HIP(this, hipMemcpyAsync(this->items.ptr, h + sz_desc, sz_items, hipMemcpyHostToDevice, stream));
+  if (sz_jobs)
+    KSG_HIP(this, hipMemcpyAsync(this->jobs.ptr, h + sz_desc + sz_items, sz_jobs,
+                                 hipMemcpyHostToDevice, stream));
+  KSG_HIP(this, hipEventRecord(staging_done, stream));
+  staging_pending = true;
+
+  // ---- pack, optional finite check, search, finalise ----
+  if (check_finite) KSG_HIP(this, hipMemsetAsync(d_flag, 0, sizeof(int), stream));
+  if (!jobs.empty()) {
+    KSG_HIP(this, launch_pack((const PackJob*)this->jobs.ptr, (int)jobs.size(), max_pad, d_flag, stream));
+  }
+  if (check_finite) {
+    // In-place columns are checked through identity jobs over their first n rows.
+    std::vector<PackJob> inplace;
+    for (int i = 0; i < np; ++i) {
+      const Problem& p = probs[i];
+      for (int a = 0; a < p.dx + p.dy + p.dz; ++a)
+        if (col_off[i][a] < 0) inplace.push_back(PackJob{p.col[a], nullptr, const_cast<float*>(p.col[a]), (int)p.n, (int)p.n});
+    }
+    std::vector<PackJob> all = jobs;
+    all.insert(all.end(), inplace.begin(), inplace.end());
+    st = check_columns_finite(all, max_pad);
+    if (st) return st;
+  }
+  const int shape = tile_variant >= 0 ? -1 : common_shape;
+  const int grid = ksg_batch_grid(shape, kp, cus);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (timing) {
+    t0 = get_event();
+    t1 = get_event();
+    if (!t0 || !t1) return fail(KSG_EDEVICE, "cannot create timing events");
+    KSG_HIP(this, hipEventRecord(t0, stream));
+  }
+  KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, (const WorkItem*)this->items.ptr,
+                                  (int)items.size(), d_counter, (const double*)htab.ptr,
+                                  (double*)partials.ptr, shape, kp, grid, stream));
+  if (timing) {
+    KSG_HIP(this, hipEventRecord(t1, stream));
+    timed.emplace_back(t0, t1);
+    for (const Problem& p : probs)
+      timed_ops += (double)p.n * (double)(p.n - 1) * (4.0 * (p.dx + p.dy + p.dz) + 2.0);
+  }
+  KSG_HIP(this, launch_finalize((const ProbDesc*)desc.ptr, np, (const double*)partials.ptr,
+                                (const double*)htab.ptr, d_out, d_counter, stream));
+  last_items = (int64_t)items.size();
+  last_grid = grid;
+  return KSG_OK;
+}
+
+// Finite check over the destinations (first n rows) of the given jobs; synchronises.
+int ksg_ctx::check_columns_finite(const std::vector<PackJob>& cols, int max_pad) {
+  if (cols.empty()) return KSG_OK;
+  const size_t sz = sizeof(PackJob) * cols.size();
+  int st = reserve(aux, sz, "finite-check jobs");
+  if (st) return st;
+  KSG_HIP(this, hipMemcpyAsync(aux.ptr, cols.data(), sz, hipMemcpyHostToDevice, stream));
+  KSG_HIP(this, launch_finite_check((const PackJob*)aux.ptr, (int)cols.size(), max_pad, d_flag, stream));
+  int flag = 0;
+  KSG_HIP(this, hipMemcpyAsync(&flag, d_flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+  KSG_HIP(this, hipStreamSynchronize(stream));
+  if (flag & 2) return fail(KSG_EINVAL, "a row permutation holds an index outside [0, N)");
+  if (flag) return fail(KSG_ENONFINITE, "input data contain NaN or infinity");
+  return KSG_OK;
+}
+
+static void fill_problem(Problem& q, const ksg_problem& p, int out_index) {
+  std::memset(&q, 0, sizeof q);
+  q.n = p.n;
+  q.dx = p.dx;
+  q.dy = p.dy;
+  q.dz = p.dz;
+  q.k = p.k;
+  const int D = p.dx + p.dy + p.dz;
+  for (int a = 0; a < D && a < kMaxDims; ++a) {
+    const float* base = a < p.dx ? p.x : (a < p.dx + p.dy ? p.y : p.z);
+    const int c = a < p.dx ? a : (a < p.dx + p.dy ? a - p.dx : a - p.dx - p.dy);
+    q.col[a] = base ? base + (int64_t)c * p.n : nullptr;
+    q.perm[a] = a < p.dx ? p.perm_x : nullptr;
+  }
+  q.eps_out = p.eps_out;
+  q.counts_out = p.counts_out;
+  q.local_out = p.local_out;
+  q.out_index = out_index;
+}
+
+extern "C" int cmi_ksg_batch(ksg_ctx* c, const ksg_problem* probs, int32_t n_probs, double* out) {
+  if (!c) return KSG_EINVAL;
+  if (n_probs < 0 || (n_probs > 0 && (!probs || !out)))
+    return c->fail(KSG_EINVAL, "cmi_ksg_batch: null problems/output or negative count");
+  std::vector<Problem> v(n_probs);
+  for (int i = 0; i < n_probs; ++i) {
+    if (probs[i].dx < 1 || probs[i].dy < 1 || probs[i].dz < 0 ||
+        probs[i].dx + probs[i].dy + probs[i].dz > KSG_MAX_DIMS)
+      return c->fail(KSG_EINVAL, "problem %d: dims (%d,%d,%d) outside d_x>=1, d_y>=1, d_z>=0, sum<=%d",
+                     i, probs[i].dx, probs[i].dy, probs[i].dz, KSG_MAX_DIMS);
+    if (probs[i].dz > 0 && !probs[i].z) return c->fail(KSG_EINVAL, "problem %d: z is NULL with d_z > 0", i);
+    fill_problem(v[i], probs[i], i);
+  }
+  KSG_HIP(c, hipSetDevice(c->device));
+  return c->run_batch(v, out);
+}
+
+extern "C" int cmi_ksg(ksg_ctx* c, const float* x, const float* y, const float* z, int64_t N,
+                       const int32_t dims[3], int32_t k, double* out_nats) {
+  if (!c) return KSG_EINVAL;
+  if (!dims || !out_nats || !x || !y) return c->fail(KSG_EINVAL, "cmi_ksg: null argument");
+  ksg_problem p;
+  std::memset(&p, 0, sizeof p);
+  p.n = N;
+  p.dx = dims[0];
+  p.dy = dims[1];
+  p.dz = dims[2];
+  p.k = k;
+  p.x = x;
+  p.y = y;
+  p.z = z;
+  int st = c->reserve(c->tmp, sizeof(double), "result");
+  if (st) return st;
+  st = cmi_ksg_batch(c, &p, 1, (double*)c->tmp.ptr);
+  if (st) return st;
+  KSG_HIP(c, hipMemcpyAsync(out_nats, c->tmp.ptr, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  KSG_HIP(c, hipStreamSynchronize(c->stream));
+  return KSG_OK;
+}
+
+// ============================================================== max statistic
+
+int ksg_ctx::maxstat_async(const double* d_cmi, int cands, int P, double alpha, int slot) {
+  if (cands < 1 || P < 1 || P > 4096)
+    return fail(KSG_EINVAL, "max statistic: need c >= 1 and 1 <= P <= 4096 (c=%d, P=%d)", cands, P);
+  if (!(alpha > 0.0 && alpha < 1.0)) return fail(KSG_EINVAL, "alpha must lie in (0, 1)");
+  KSG_HIP(this, launch_maxstat(d_cmi, cands, P, alpha, d_ms + slot, stream));
+  KSG_HIP(this, hipMemcpyAsync(h_ms + slot, d_ms + slot, sizeof(MaxStatOut), hipMemcpyDeviceToHost, stream));
+  return KSG_OK;
+}
+
+static void to_public(const MaxStatOut& m, ksg_maxstat_result* out) {
+  out->c_star = m.c_star;
+  out->count = m.count;
+  out->significant = m.significant;
+  out->n_perm = m.n_perm;
+  out->t_obs = m.t_obs;
+  out->pval = m.pval;
+  out->tau05 = m.tau05;
+  out->tau01 = m.tau01;
+}
+
+extern "C" int ksg_maxstat(ksg_ctx* c, const double* cmi, int32_t cands, int32_t P, double alpha,
+                           ksg_maxstat_result* out) {
+  if (!c) return KSG_EINVAL;
+  if (!cmi || !out) return c->fail(KSG_EINVAL, "ksg_maxstat: null argument");
+  KSG_HIP(c, hipSetDevice(c->device));
+  int st = c->maxstat_async(cmi, cands, P, alpha, 0);
+  if (st) return st;
+  KSG_HIP(c, hipStreamSynchronize(c->stream));
+  to_public(c->h_ms[0], out);
+  return KSG_OK;
+}
+
+// ============================================================== embedding
+
+extern "C" int ksg_embed(ksg_ctx* c, const float* data, int32_t n_vars, int64_t T, int32_t n_trials,
+                         int32_t target, int32_t max_lag, float* cand_out, float* y_out) {
+  if (!c) return KSG_EINVAL;
+  if (!data || !cand_out || !y_out) return c->fail(KSG_EINVAL, "ksg_embed: null argument");
+  if (n_vars < 1 || n_trials < 1 || max_lag < 1 || T <= max_lag || target < 0 || target >= n_vars)
+    return c->fail(KSG_EINVAL, "ksg_embed: bad sizes (n_vars=%d T=%lld n_trials=%d target=%d max_lag=%d)",
+                   n_vars, (long long)T, n_trials, target, max_lag);
+  const int64_t N = (int64_t)n_trials * (T - max_lag);
+  if (N > (int64_t)INT32_MAX - 1024) return c->fail(KSG_EINVAL, "ksg_embed: N too large");
+  KSG_HIP(c, hipSetDevice(c->device));
+  KSG_HIP(c, launch_embed(data, n_vars, T, n_trials, target, max_lag, cand_out, y_out, N, c->stream));
+  return KSG_OK;
+}
+
+// ============================================================== timing
+
+hipEvent_t ksg_ctx::get_event() {
+  if (!event_pool.empty()) {
+    hipEvent_t e = event_pool.back();
+    event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+extern "C" int ksg_take_timing(ksg_ctx* c, double* ms, int64_t* launches, double* ops) {
+  if (!c) return KSG_EINVAL;
+  if (!ms || !launches || !ops) return c->fail(KSG_EINVAL, "ksg_take_timing: null output");
+  KSG_HIP(c, hipStreamSynchronize(c->stream));
+  double total = 0.0;
+  for (auto& pr : c->timed) {
+    float t = 0.0f;
+    KSG_HIP(c, hipEventElapsedTime(&t, pr.first, pr.second));
+    total += t;
+    c->event_pool.push_back(pr.first);
+    c->event_pool.push_back(pr.second);
+  }
+  *ms = total;
+  *launches = (int64_t)c->timed.size();
+  *ops = c->timed_ops;
+  c->timed.clear();
+  c->timed_ops = 0.0;
+  return KSG_OK;
+}

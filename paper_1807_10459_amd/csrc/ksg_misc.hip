@@ -1,0 +1,236 @@
+// Data movement and statistics kernels around the search kernel:
+//  - column packing (SoA copy / permutation gather into +inf-padded columns),
+//  - the finite-data check,
+//  - lagged embedding of [trials][vars][T] series into candidate columns,
+//  - per-problem finalisation of the digamma sum,
+//  - the max-statistic surrogate test.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace ksg {
+
+extern const void* search_kernels_kp5[40];
+extern const void* search_kernels_kp9[40];
+extern const void* search_kernels_kp17[40];
+
+// ------------------------------------------------------------------ packing
+
+// grid.x: chunks of 1024 rows, grid.y: jobs (strided).  dst[i] = src[perm[i]] or src[i]; pad +inf.
+// A gather index outside [0, n) is never dereferenced: the row becomes NaN and bit 1 of
+// *flag is set (the finite check then reports the batch as invalid).
+__global__ __launch_bounds__(256) void pack_kernel(const PackJob* __restrict__ jobs, int n_jobs,
+                                                   int* __restrict__ flag) {
+  for (int jb = blockIdx.y; jb < n_jobs; jb += gridDim.y) {
+    const PackJob job = jobs[jb];
+    const int base = blockIdx.x * 1024;
+    if (base >= job.n_pad) continue;
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = base + r * 256 + threadIdx.x;
+      if (i < job.n) {
+        int src = i;
+        if (job.perm) {
+          src = job.perm[i];
+          if ((unsigned)src >= (unsigned)job.n) {
+            bad = true;
+            job.dst[i] = NAN;
+            continue;
+          }
+        }
+        job.dst[i] = job.src[src];
+      } else if (i < job.n_pad) {
+        job.dst[i] = INFINITY;
+      }
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 2);
+  }
+}
+
+hipError_t launch_pack(const PackJob* d_jobs, int n_jobs, int max_pad, int* d_flag, hipStream_t stream) {
+  if (n_jobs <= 0) return hipSuccess;
+  dim3 grid((max_pad + 1023) / 1024, n_jobs < 65535 ? n_jobs : 65535);
+  hipLaunchKernelGGL(pack_kernel, grid, dim3(256), 0, stream, d_jobs, n_jobs, d_flag);
+  return hipGetLastError();
+}
+
+// Sets *flag = 1 when any of the first n rows of a job's destination is NaN or +-inf.
+__global__ __launch_bounds__(256) void finite_kernel(const PackJob* __restrict__ jobs, int n_jobs,
+                                                     int* __restrict__ flag) {
+  for (int jb = blockIdx.y; jb < n_jobs; jb += gridDim.y) {
+    const PackJob job = jobs[jb];
+    const int base = blockIdx.x * 1024;
+    if (base >= job.n) continue;
+    bool bad = false;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = base + r * 256 + threadIdx.x;
+      if (i < job.n) bad |= !isfinite(job.dst[i]);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+  }
+}
+
+hipError_t launch_finite_check(const PackJob* d_jobs, int n_jobs, int max_pad, int* d_flag,
+                               hipStream_t stream) {
+  if (n_jobs <= 0) return hipSuccess;
+  dim3 grid((max_pad + 1023) / 1024, n_jobs < 65535 ? n_jobs : 65535);
+  hipLaunchKernelGGL(finite_kernel, grid, dim3(256), 0, stream, d_jobs, n_jobs, d_flag);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ embedding
+
+// Candidate (v, l) row i: trial tr = i / (T - L), time t = L + i % (T - L), value x_v(t - l).
+// grid.x: row chunks of 256, grid.y: columns (n_vars * L candidates + 1 target column).
+__global__ __launch_bounds__(256) void embed_kernel(const float* __restrict__ data, int n_vars,
+                                                    int64_t T, int n_trials, int target, int L,
+                                                    float* __restrict__ cand, float* __restrict__ y,
+                                                    int64_t stride) {
+  const int c = blockIdx.y;
+  const int64_t per_trial = T - L;
+  const int64_t n = per_trial * n_trials;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= stride) return;
+  const bool is_target = (c == n_vars * L);
+  float* dst = is_target ? y : cand + (int64_t)c * stride;
+  if (i >= n) {
+    dst[i] = INFINITY;
+    return;
+  }
+  const int v = is_target ? target : c / L;
+  const int lag = is_target ? 0 : (c % L) + 1;
+  const int64_t tr = i / per_trial;
+  const int64_t t = L + (i - tr * per_trial);
+  dst[i] = data[(tr * n_vars + v) * T + (t - lag)];
+}
+
+hipError_t launch_embed(const float* data, int n_vars, int64_t T, int n_trials, int target,
+                        int max_lag, float* cand, float* y, int64_t col_stride, hipStream_t stream) {
+  dim3 grid((unsigned)((col_stride + 255) / 256), n_vars * max_lag + 1);
+  hipLaunchKernelGGL(embed_kernel, grid, dim3(256), 0, stream, data, n_vars, T, n_trials, target,
+                     max_lag, cand, y, col_stride);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ finalisation
+
+// I = H_{k-1} - S / N, S = compensated (Neumaier) sum of the problem's tile partials in tile
+// order.  Thread 0 also re-arms the work counter of the search kernel for the next launch.
+__global__ __launch_bounds__(256) void finalize_kernel(const ProbDesc* __restrict__ descs, int n_probs,
+                                                       const double* __restrict__ partials,
+                                                       const double* __restrict__ htab,
+                                                       double* __restrict__ out,
+                                                       int* __restrict__ counter) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) *counter = 0;
+  if (p >= n_probs) return;
+  const ProbDesc& d = descs[p];
+  double s = 0.0, comp = 0.0;
+  for (int t = 0; t < d.n_tiles; ++t) {
+    const double v = partials[d.part_base + t];
+    const double u = s + v;
+    comp += (fabs(s) >= fabs(v)) ? (s - u) + v : (v - u) + s;
+    s = u;
+  }
+  s += comp;
+  out[d.out_index] = htab[d.k - 1] - s / (double)d.n;
+}
+
+static const void* pick_search_kernel(int shape, int kp) {
+  const void* const* table = kp <= 5 ? search_kernels_kp5 : (kp <= 9 ? search_kernels_kp9 : search_kernels_kp17);
+  if (shape >= 0 && shape < 39) return table[shape];
+  return table[39];
+}
+
+int ksg_batch_grid(int shape, int kp, int device_cus) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick_search_kernel(shape, kp), kTileQ, 0) !=
+          hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  return per_cu * device_cus;
+}
+
+hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
+                             int* d_counter, const double* d_htab, double* d_partials, int shape,
+                             int kp, int grid, hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  const void* fn = pick_search_kernel(shape, kp);
+  const ProbDesc* a0 = d_desc;
+  const WorkItem* a1 = d_items;
+  int a2 = n_items;
+  int* a3 = d_counter;
+  const double* a4 = d_htab;
+  double* a5 = d_partials;
+  void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5};
+  const int g = grid < n_items ? grid : n_items;
+  return hipLaunchKernel(fn, dim3(g), dim3(kTileQ), args, 0, stream);
+}
+
+hipError_t launch_finalize(const ProbDesc* d_desc, int n_probs, const double* d_partials,
+                           const double* d_htab, double* d_out, int* d_counter, hipStream_t stream) {
+  hipLaunchKernelGGL(finalize_kernel, dim3((n_probs + 255) / 256), dim3(256), 0, stream, d_desc,
+                     n_probs, d_partials, d_htab, d_out, d_counter);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ max statistic
+
+// One block.  cmi: [c][P+1], column 0 = originals.  T_p = max_c cmi[c][p]; count of T_p >= t_obs;
+// thresholds by stable descending rank (rank r-1 is the r-th largest).
+constexpr int kMaxPerm = 4096;
+
+__global__ __launch_bounds__(1024) void maxstat_kernel(const double* __restrict__ cmi, int c, int P,
+                                                       double alpha, MaxStatOut* __restrict__ out) {
+  __shared__ double tmax[kMaxPerm];
+  __shared__ int s_count;
+  __shared__ int s_cstar;
+  if (threadIdx.x == 0) {
+    int best = 0;
+    for (int i = 1; i < c; ++i)
+      if (cmi[(int64_t)i * (P + 1)] > cmi[(int64_t)best * (P + 1)]) best = i;
+    s_cstar = best;
+    s_count = 0;
+  }
+  __syncthreads();
+  const double t_obs = cmi[(int64_t)s_cstar * (P + 1)];
+  int local = 0;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    double m = cmi[p + 1];
+    for (int i = 1; i < c; ++i) m = fmax(m, cmi[(int64_t)i * (P + 1) + p + 1]);
+    tmax[p] = m;
+    local += (m >= t_obs) ? 1 : 0;
+  }
+  atomicAdd(&s_count, local);
+  __syncthreads();
+  const int r05 = min(max((int)ceil(0.05 * P), 1), P);
+  const int r01 = min(max((int)ceil(0.01 * P), 1), P);
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const double v = tmax[p];
+    int rank = 0;
+    for (int q = 0; q < P; ++q) rank += (tmax[q] > v) || (tmax[q] == v && q < p);
+    if (rank == r05 - 1) out->tau05 = v;
+    if (rank == r01 - 1) out->tau01 = v;
+  }
+  if (threadIdx.x == 0) {
+    const double pval = (double)s_count / (double)P;
+    out->c_star = s_cstar;
+    out->count = s_count;
+    out->n_perm = P;
+    out->t_obs = t_obs;
+    out->pval = pval;
+    out->significant = pval < alpha ? 1 : 0;
+  }
+}
+
+hipError_t launch_maxstat(const double* cmi, int c, int n_perm, double alpha, MaxStatOut* out,
+                          hipStream_t stream) {
+  if (n_perm > kMaxPerm || n_perm < 1 || c < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(maxstat_kernel, dim3(1), dim3(1024), 0, stream, cmi, c, n_perm, alpha, out);
+  return hipGetLastError();
+}
+
+}  // namespace ksg

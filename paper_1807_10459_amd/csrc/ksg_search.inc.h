@@ -1,0 +1,315 @@
+// KSG search kernel: brute-force max-norm k-th neighbour radius, strict subspace range
+// counts and the FP64 harmonic-number partial sum of one 256-query tile.
+//
+// Estimator (KSG algorithm 1 in the conditional form of Frenzel & Pompe; the paper names
+// the KSG estimator in its Summary, estimator paragraph, without printing it):
+//   eps_i  = k-th smallest joint max-norm distance to the other points,
+//   n_S(i) = #{ j != i : d^S_ij < eps_i } for S in {XZ, YZ, Z},
+//   term_i = H_{n_XZ(i)} + H_{n_YZ(i)} - H_{n_Z(i)},  I = H_{k-1} - (1/N) sum_i term_i.
+//
+// Mapping to CDNA4.  One query per lane, 4 waves per work item.  Reference points are
+// read through the scalar data path (constant address space, wave-uniform addresses), so
+// every reference coordinate arrives in an SGPR and feeds v_sub_f32 as its scalar operand:
+// no LDS traffic and no VGPRs are spent on references, and the VALU does only the
+// estimator's own arithmetic (sub, max with |.| source modifiers folded into v_max3,
+// compare).  Self is not skipped: d_ii = 0 is always among the k+1 smallest, so the
+// (k+1)-th smallest of all N distances is eps_i, and every count includes self exactly
+// when eps_i > 0, which the epilogue subtracts.  Padding rows are +inf in every column,
+// so they never enter the top-k or a count.
+//
+// Top-k: KP sorted registers, ascending; the first KP-1-k hold -inf (inert), the last
+// k+1 the smallest distances seen; insertion is KP-1 v_med3_f32 + 1 v_min_f32 and runs only
+// when some lane of the wave has a candidate below its current radius.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+
+#define KSG_AS4 __attribute__((address_space(4)))
+
+namespace ksg {
+
+typedef const KSG_AS4 float* cfptr;
+
+template <int KP>
+__device__ __forceinline__ void topk_insert(float (&b)[KP], float d) {
+#pragma unroll
+  for (int i = KP - 1; i >= 1; --i) b[i] = __builtin_amdgcn_fmed3f(b[i - 1], b[i], d);
+  b[0] = __builtin_amdgcn_fmed3f(-INFINITY, b[0], d);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Tile epilogue shared by all shapes: self correction, optional per-point outputs,
+// FP64 digamma terms, deterministic block reduction, one partial per work item.
+__device__ __forceinline__ void tile_epilogue(const KSG_AS4 ProbDesc* pd, int tile, int qi,
+                                              bool valid, float eps, int cxz, int cyz, int cz,
+                                              bool z_empty, const double* __restrict__ htab,
+                                              double* __restrict__ partials, double* s_red) {
+  const int n = pd->n;
+  const int self = eps > 0.0f ? 1 : 0;
+  // Clamped at 0 so that table reads stay in range even for non-finite data (whose
+  // self-distance is NaN) when the finite check has been switched off.
+  const int nxz = max(cxz - self, 0);
+  const int nyz = max(cyz - self, 0);
+  const int nz = z_empty ? (self ? n - 1 : 0) : max(cz - self, 0);
+  double t = 0.0;
+  if (valid) {
+    t = (htab[nxz] + htab[nyz]) - htab[nz];
+    float* eo = pd->eps_out;
+    int32_t* co = pd->counts_out;
+    double* lo = pd->local_out;
+    if (eo) eo[qi] = eps;
+    if (co) {
+      const int sw = pd->swap_xy;
+      co[qi] = sw ? nyz : nxz;
+      co[n + qi] = sw ? nxz : nyz;
+      co[2 * n + qi] = nz;
+    }
+    if (lo) lo[qi] = htab[pd->k - 1] - t;
+  }
+  t = wave_sum(t);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) s_red[wave] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) partials[pd->part_base + tile] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+}
+
+// Fast path: compile-time subspace dimensions.
+template <int DX, int DY, int DZ, int KP, int U>
+__device__ __forceinline__ void search_tile(const KSG_AS4 ProbDesc* pd, int tile,
+                                            const double* __restrict__ htab,
+                                            double* __restrict__ partials, double* s_red) {
+  constexpr int D = DX + DY + DZ;
+  const int n = pd->n;
+  const int n_pad = pd->n_pad;
+  const int k = pd->k;
+  const int qraw = tile * kTileQ + (int)threadIdx.x;
+  const bool valid = qraw < n;
+  const int qi = valid ? qraw : n - 1;
+
+  cfptr col[D];
+  float q[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float* c = pd->col[a];
+    col[a] = (cfptr)c;
+    q[a] = c[qi];
+  }
+
+  // ---- pass 1: the (k+1) smallest joint distances, self included ----
+  float b[KP];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) b[i] = (i < KP - 1 - k) ? -INFINITY : INFINITY;
+
+  for (int j = 0; j < n_pad; j += U) {
+    float d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) d[u] = fabsf(col[0][j + u] - q[0]);
+#pragma unroll
+    for (int a = 1; a < D; ++a) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) d[u] = fmaxf(d[u], fabsf(col[a][j + u] - q[a]));
+    }
+    bool hit = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) hit |= d[u] < b[KP - 1];
+    if (hit) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) topk_insert<KP>(b, d[u]);
+    }
+  }
+  const float eps = b[KP - 1];
+
+  // ---- pass 2: strict counts in XZ, YZ and Z (self included, removed in the epilogue) ----
+  // One accumulator per unrolled reference keeps every count a compare + add-with-carry.
+  unsigned axz[U], ayz[U], az[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) axz[u] = ayz[u] = az[u] = 0u;
+  for (int j = 0; j < n_pad; j += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float A = fabsf(col[0][j + u] - q[0]);
+#pragma unroll
+      for (int a = 1; a < DX; ++a) A = fmaxf(A, fabsf(col[a][j + u] - q[a]));
+      float B = fabsf(col[DX][j + u] - q[DX]);
+#pragma unroll
+      for (int a = DX + 1; a < DX + DY; ++a) B = fmaxf(B, fabsf(col[a][j + u] - q[a]));
+      if constexpr (DZ > 0) {
+        float C = fabsf(col[DX + DY][j + u] - q[DX + DY]);
+#pragma unroll
+        for (int a = DX + DY + 1; a < D; ++a) C = fmaxf(C, fabsf(col[a][j + u] - q[a]));
+        axz[u] += (unsigned)(fmaxf(A, C) < eps);
+        ayz[u] += (unsigned)(fmaxf(B, C) < eps);
+        az[u] += (unsigned)(C < eps);
+      } else {
+        axz[u] += (unsigned)(A < eps);
+        ayz[u] += (unsigned)(B < eps);
+      }
+    }
+  }
+  int cxz = 0, cyz = 0, cz = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    cxz += (int)axz[u];
+    cyz += (int)ayz[u];
+    cz += (int)az[u];
+  }
+  tile_epilogue(pd, tile, qi, valid, eps, cxz, cyz, cz, DZ == 0, htab, partials, s_red);
+}
+
+// Generic path: any split of up to kMaxDims dimensions, subspace membership resolved
+// with wave-uniform selects.  Used for shapes outside the fast table.
+template <int D, int KP>
+__device__ __forceinline__ void search_tile_generic(const KSG_AS4 ProbDesc* pd, int tile,
+                                                    const double* __restrict__ htab,
+                                                    double* __restrict__ partials,
+                                                    double* s_red) {
+  constexpr int U = 4;
+  const int n = pd->n;
+  const int n_pad = pd->n_pad;
+  const int k = pd->k;
+  const int dx = pd->dx, dy = pd->dy;
+  const int qraw = tile * kTileQ + (int)threadIdx.x;
+  const bool valid = qraw < n;
+  const int qi = valid ? qraw : n - 1;
+  cfptr col[D];
+  float q[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float* c = pd->col[a];
+    col[a] = (cfptr)c;
+    q[a] = c[qi];
+  }
+  float b[KP];
+#pragma unroll
+  for (int i = 0; i < KP; ++i) b[i] = (i < KP - 1 - k) ? -INFINITY : INFINITY;
+  for (int j = 0; j < n_pad; j += U) {
+    float d[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) d[u] = fabsf(col[0][j + u] - q[0]);
+#pragma unroll
+    for (int a = 1; a < D; ++a) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) d[u] = fmaxf(d[u], fabsf(col[a][j + u] - q[a]));
+    }
+    bool hit = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) hit |= d[u] < b[KP - 1];
+    if (hit) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) topk_insert<KP>(b, d[u]);
+    }
+  }
+  const float eps = b[KP - 1];
+  const bool z_empty = (dx + dy == D);
+  int cxz = 0, cyz = 0, cz = 0;
+  for (int j = 0; j < n_pad; j += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float A = 0.0f, B = 0.0f, C = 0.0f;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const float t = fabsf(col[a][j + u] - q[a]);
+        if (a < dx) A = fmaxf(A, t);
+        else if (a < dx + dy) B = fmaxf(B, t);
+        else C = fmaxf(C, t);
+      }
+      cxz += fmaxf(A, C) < eps;
+      cyz += fmaxf(B, C) < eps;
+      cz += C < eps;
+    }
+  }
+  tile_epilogue(pd, tile, qi, valid, eps, cxz, cyz, cz, z_empty, htab, partials, s_red);
+}
+
+// Fast-shape dispatch: shape = pair * (kFastMaxDz + 1) + dz.
+template <int KP>
+__device__ __forceinline__ void dispatch_fast(int shape, const KSG_AS4 ProbDesc* pd, int tile,
+                                              const double* __restrict__ htab,
+                                              double* __restrict__ partials, double* s_red);
+
+#define KSG_FAST_CASE(PAIR, DXv, DYv, DZv)                                                      \
+  case (PAIR) * (kFastMaxDz + 1) + (DZv):                                                       \
+    search_tile<DXv, DYv, DZv, KP, ((DXv + DYv + DZv) <= 8 ? 8 : 4)>(pd, tile, htab, partials, \
+                                                                     s_red);                    \
+    break;
+
+#define KSG_FAST_PAIR(PAIR, DXv, DYv)                                                \
+  KSG_FAST_CASE(PAIR, DXv, DYv, 0) KSG_FAST_CASE(PAIR, DXv, DYv, 1)                  \
+  KSG_FAST_CASE(PAIR, DXv, DYv, 2) KSG_FAST_CASE(PAIR, DXv, DYv, 3)                  \
+  KSG_FAST_CASE(PAIR, DXv, DYv, 4) KSG_FAST_CASE(PAIR, DXv, DYv, 5)                  \
+  KSG_FAST_CASE(PAIR, DXv, DYv, 6) KSG_FAST_CASE(PAIR, DXv, DYv, 7)                  \
+  KSG_FAST_CASE(PAIR, DXv, DYv, 8) KSG_FAST_CASE(PAIR, DXv, DYv, 9)                  \
+  KSG_FAST_CASE(PAIR, DXv, DYv, 10) KSG_FAST_CASE(PAIR, DXv, DYv, 11)                \
+  KSG_FAST_CASE(PAIR, DXv, DYv, 12)
+
+#define KSG_GENERIC_CASE(Dv) \
+  case Dv:                   \
+    search_tile_generic<Dv, KP>(pd, tile, htab, partials, s_red); \
+    break;
+
+template <int KP>
+__device__ __forceinline__ void dispatch_generic(int D, const KSG_AS4 ProbDesc* pd, int tile,
+                                                 const double* __restrict__ htab,
+                                                 double* __restrict__ partials, double* s_red) {
+  switch (D) {
+    KSG_GENERIC_CASE(2) KSG_GENERIC_CASE(3) KSG_GENERIC_CASE(4) KSG_GENERIC_CASE(5)
+    KSG_GENERIC_CASE(6) KSG_GENERIC_CASE(7) KSG_GENERIC_CASE(8) KSG_GENERIC_CASE(9)
+    KSG_GENERIC_CASE(10) KSG_GENERIC_CASE(11) KSG_GENERIC_CASE(12) KSG_GENERIC_CASE(13)
+    KSG_GENERIC_CASE(14) KSG_GENERIC_CASE(15) KSG_GENERIC_CASE(16)
+    default: break;
+  }
+}
+
+// Persistent batched kernel.  SHAPE >= 0: every problem of the launch has that fast shape;
+// SHAPE == -1: mixed batch, per-problem dispatch.  Work items are claimed with one atomic per
+// item from a counter that the finalisation kernel resets to zero.
+template <int SHAPE, int KP>
+__global__ __launch_bounds__(kTileQ) void ksg_batch_kernel(const ProbDesc* __restrict__ descs,
+                                                           const WorkItem* __restrict__ items,
+                                                           int n_items, int* __restrict__ counter,
+                                                           const double* __restrict__ htab,
+                                                           double* __restrict__ partials) {
+  __shared__ int s_item;
+  __shared__ double s_red[kTileQ / 64];
+  const KSG_AS4 ProbDesc* d4 = (const KSG_AS4 ProbDesc*)descs;
+  const KSG_AS4 WorkItem* i4 = (const KSG_AS4 WorkItem*)items;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= n_items) break;
+    const int prob = i4[it].prob;
+    const int tile = i4[it].tile;
+    const KSG_AS4 ProbDesc* pd = d4 + prob;
+    if constexpr (SHAPE >= 0 && SHAPE < kGenericShape) {
+      constexpr int PAIR = SHAPE / (kFastMaxDz + 1);
+      constexpr int DZ = SHAPE % (kFastMaxDz + 1);
+      constexpr int DX = PAIR == 2 ? 2 : 1;
+      constexpr int DY = PAIR == 0 ? 1 : 2;
+      search_tile<DX, DY, DZ, KP, ((DX + DY + DZ) <= 8 ? 8 : 4)>(pd, tile, htab, partials, s_red);
+    } else {
+      const int shape = pd->variant;
+      if (shape >= kGenericShape) {
+        dispatch_generic<KP>(pd->dx + pd->dy + pd->dz, pd, tile, htab, partials, s_red);
+      } else {
+        switch (shape) {
+          KSG_FAST_PAIR(0, 1, 1)
+          KSG_FAST_PAIR(1, 1, 2)
+          KSG_FAST_PAIR(2, 2, 2)
+          default: break;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace ksg

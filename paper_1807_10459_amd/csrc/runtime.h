@@ -1,0 +1,83 @@
+// Host-side context of the library (the opaque ksg_ctx of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <string>
+#include <vector>
+
+#include "../../include/ksgcmi.h"
+#include "internal.h"
+
+namespace ksg {
+
+// A grow-only device allocation owned by the context.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t cap = 0;
+};
+
+// One CMI problem in the engine's own form: one pointer per dimension (X..., Y..., Z...),
+// an optional row gather per dimension, and whether the column is already a +inf-padded
+// device column (then it is used in place unless gathered).
+struct Problem {
+  int64_t n;
+  int dx, dy, dz, k;
+  const float* col[kMaxDims];
+  const int32_t* perm[kMaxDims];
+  bool padded[kMaxDims];
+  float* eps_out;
+  int32_t* counts_out;
+  double* local_out;
+  int out_index;
+};
+
+}  // namespace ksg
+
+void ksg_build_harmonic(int64_t nmax, double* out);
+
+struct ksg_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int cus = 0;
+  char arch[64] = {0};
+  std::string err;
+
+  bool check_finite = true;
+  int tile_variant = -1;
+  bool use_graph = true;
+
+  ksg::DevBuf htab, pool, desc, items, partials, jobs, tmp, embed, cmi, aux, feat;
+  int64_t htab_n = 0;
+  int* d_counter = nullptr;  // [0]: search work counter, [1]: finite flag
+  int* d_flag = nullptr;
+  ksg::MaxStatOut* d_ms = nullptr;
+  ksg::MaxStatOut* h_ms = nullptr;  // pinned
+
+  void* staging = nullptr;  // pinned upload block
+  size_t staging_cap = 0;
+  hipEvent_t staging_done = nullptr;
+  bool staging_pending = false;
+
+  int64_t last_items = 0;
+  int last_grid = 0;
+
+  // KSG_OPT_TIMING: events around each search launch, harvested by ksg_take_timing.
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
+  std::vector<hipEvent_t> event_pool;
+  double timed_ops = 0.0;
+  hipEvent_t get_event();
+
+  int fail(int status, const char* fmt, ...);
+  int hip_fail(hipError_t e, const char* what);
+  int reserve(ksg::DevBuf& b, size_t bytes, const char* what);
+  int reserve_host(size_t bytes);
+  int wait_staging();
+  int ensure_htab(int64_t n);
+  int validate(const ksg::Problem& p, int index);
+  int run_batch(const std::vector<ksg::Problem>& probs, double* d_out);
+  int check_columns_finite(const std::vector<ksg::PackJob>& cols, int max_pad);
+  int maxstat_async(const double* d_cmi, int cands, int P, double alpha, int slot);
+};

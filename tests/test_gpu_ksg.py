@@ -1,0 +1,212 @@
+"""Parity of the HIP estimator with the CPU oracle (needs an MI355X).
+
+Counts and radii must match bit for bit; CMI values within 1e-12 * max(|I|, 1 nat).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle.ksg import ksg_cmi, ksg_cmi_from_counts, ksg_counts, ksg_point_counts, local_terms
+from tests.gpu_util import dev, soa, tol
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def _run(lib, ctx, x, y, z, k, perm=None):
+    """GPU eps, counts, local terms and CMI of one problem via the batch entry point."""
+    import torch
+    n = np.asarray(x).shape[0]
+    eps = torch.empty(n, dtype=torch.float32, device="cuda")
+    cnt = torch.empty((3, n), dtype=torch.int32, device="cuda")
+    loc = torch.empty(n, dtype=torch.float64, device="cuda")
+    p = lib.Problem(soa(x), soa(y), soa(z), k, perm_x=None if perm is None else dev(perm),
+                    eps_out=eps, counts_out=cnt, local_out=loc)
+    out = ctx.cmi_batch([p])
+    torch.cuda.synchronize()
+    return eps.cpu().numpy(), cnt.cpu().numpy(), loc.cpu().numpy(), float(out.cpu()[0])
+
+
+def _check_full(lib, ctx, x, y, z, k, label=""):
+    eps, cnt, loc, cmi = _run(lib, ctx, x, y, z, k)
+    e, a, b, c = ksg_counts(x, y, z, k)
+    assert np.array_equal(eps, e), label
+    assert np.array_equal(cnt[0], a), label
+    assert np.array_equal(cnt[1], b), label
+    assert np.array_equal(cnt[2], c), label
+    n = np.asarray(x).shape[0]
+    ref = ksg_cmi_from_counts(n, k, a, b, c)
+    assert abs(cmi - ref) <= tol(ref), (label, cmi, ref)
+    lt = local_terms(n, k, a, b, c)
+    assert np.allclose(loc, lt, rtol=0, atol=1e-13), label
+    return cmi
+
+
+def test_worked_example(lib, ctx):
+    g = json.load(open(os.path.join(GOLD, "ksg_tiny_ties.json")))
+    x, y, z = (np.array(g[c], np.float32) for c in "xyz")
+    cmi = _check_full(lib, ctx, x, y, z, g["k"])
+    assert abs(cmi - 137 / 180) < 1e-15
+    assert abs(_check_full(lib, ctx, x, y, None, g["k"]) - 161 / 180) < 1e-15
+
+
+def test_fp32_discriminator(lib, ctx):
+    g = json.load(open(os.path.join(GOLD, "fp32_discriminator.json")))
+    x, y = np.array(g["x"], np.float32), np.array(g["y"], np.float32)
+    eps, cnt, _, _ = _run(lib, ctx, x, y, None, 1)
+    assert eps[0] == g["eps0"] and cnt[0][0] == g["n_x0"]
+
+
+def test_single_entry_point_c0(lib, ctx):
+    p, _, _ = workloads.gaussian_trivariate(seed=0, n_perm=0)
+    ref = ksg_cmi(p.x, p.y, p.z, 4)
+    got = ctx.cmi(soa(p.x), soa(p.y), soa(p.z), 4)
+    assert abs(got - ref) <= tol(ref)
+    _check_full(lib, ctx, p.x, p.y, p.z, 4, "c0")
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 0), (1, 1, 1), (1, 1, 5), (1, 2, 3), (2, 1, 2), (2, 2, 4),
+                                  (1, 1, 12), (3, 1, 2), (1, 4, 0), (2, 3, 5), (5, 5, 6), (1, 1, 14)])
+@pytest.mark.parametrize("k", [4, 8])
+def test_shapes_ragged(lib, ctx, dims, k):
+    # N spans several 256-query tiles and ends in a ragged tile and a ragged 64-row pad
+    n = 777 + 13 * sum(dims)
+    p = workloads.random_problem(sum(dims) * 7 + k, n, *dims, k)
+    _check_full(lib, ctx, p.x, p.y, p.z, k, str(dims))
+
+
+@pytest.mark.parametrize("kind", ["grid", "unit12"])
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 16])
+def test_ties_and_small_k(lib, ctx, kind, k):
+    p = workloads.random_problem(40 + k, 300, 1, 2, 2, k, kind=kind)
+    _check_full(lib, ctx, p.x, p.y, p.z, k, kind)
+
+
+def test_duplicates_and_zero_radius(lib, ctx):
+    g = workloads.rng(77)
+    x = g.integers(0, 3, size=(500, 1)).astype(np.float32)
+    y = g.integers(0, 3, size=(500, 1)).astype(np.float32)
+    z = g.integers(0, 2, size=(500, 1)).astype(np.float32)
+    for k in (1, 4, 8):
+        _check_full(lib, ctx, x, y, z, k, f"dup k={k}")
+        _check_full(lib, ctx, x, y, None, k, f"dup z-empty k={k}")
+
+
+@pytest.mark.parametrize("n", [2, 5, 63, 64, 65, 255, 256, 257])
+def test_smallest_sizes(lib, ctx, n):
+    k = 1
+    p = workloads.random_problem(n, n, 1, 1, 1, k)
+    _check_full(lib, ctx, p.x, p.y, p.z, k, f"n={n}")
+
+
+def test_denormals_and_large_magnitudes(lib, ctx):
+    g = workloads.rng(5)
+    x = (g.standard_normal((400, 1)) * 1e-39).astype(np.float32)  # subnormal FP32 values
+    y = (g.standard_normal((400, 1)) * 1e30).astype(np.float32)
+    z = (g.standard_normal((400, 1))).astype(np.float32)
+    assert np.any((np.abs(x) < np.finfo(np.float32).tiny) & (x != 0))
+    _check_full(lib, ctx, x, y, z, 4, "denormal")
+
+
+def test_surrogate_gather(lib, ctx):
+    p, perms, _ = workloads.gaussian_trivariate(seed=0, n_perm=3)
+    for q in range(3):
+        eps, cnt, _, cmi = _run(lib, ctx, p.x, p.y, p.z, 4, perm=perms[q])
+        e, a, b, c = ksg_counts(p.x[perms[q]], p.y, p.z, 4)
+        assert np.array_equal(eps, e) and np.array_equal(cnt[0], a) and np.array_equal(cnt[2], c)
+        ref = ksg_cmi_from_counts(p.n, 4, a, b, c)
+        assert abs(cmi - ref) <= tol(ref)
+
+
+def test_c0_with_200_surrogates_batch(lib, ctx):
+    import torch
+    p, perms, _ = workloads.gaussian_trivariate(seed=0, n_perm=200)
+    x, y, z = soa(p.x), soa(p.y), soa(p.z)
+    dperm = dev(perms)
+    probs = [lib.Problem(x, y, z, 4)] + [lib.Problem(x, y, z, 4, perm_x=dperm[q]) for q in range(200)]
+    out = ctx.cmi_batch(probs).cpu().numpy()
+    for q in [0, 1, 2, 57, 133, 199]:
+        xs = p.x if q == 0 else p.x[perms[q - 1]]
+        ref = ksg_cmi(xs, p.y, p.z, 4)
+        assert abs(out[q] - ref) <= tol(ref), q
+    # batch result == single-call result, bit for bit
+    assert out[0] == ctx.cmi(x, y, z, 4)
+
+
+def test_uneven_batch_sampled(lib, ctx):
+    """The 64-problem uneven batch: every problem checked on sampled points and by the count
+    inequalities; the smaller problems also in full."""
+    import torch
+    probs, _ = workloads.uneven_batch(seed=2)
+    tens = []
+    outs = []
+    for pr in probs:
+        eps = torch.empty(pr.n, dtype=torch.float32, device="cuda")
+        cnt = torch.empty((3, pr.n), dtype=torch.int32, device="cuda")
+        tens.append(lib.Problem(soa(pr.x), soa(pr.y), soa(pr.z), pr.k, eps_out=eps, counts_out=cnt))
+        outs.append((eps, cnt))
+    res = ctx.cmi_batch(tens).cpu().numpy()
+    g = workloads.rng(99)
+    n_full = 0
+    for i, pr in enumerate(probs):
+        eps = outs[i][0].cpu().numpy()
+        cnt = outs[i][1].cpu().numpy().astype(np.int64)
+        assert np.all(cnt[0] <= cnt[2]) and np.all(cnt[1] <= cnt[2]), i
+        for q in list(g.choice(pr.n, 6, replace=False)) + [0, pr.n - 1]:
+            e, a, b, c = ksg_point_counts(pr.x, pr.y, pr.z, pr.k, int(q))
+            assert eps[q] == e and cnt[0][q] == a and cnt[1][q] == b and cnt[2][q] == c, (i, q)
+        # the FP64 sum over the device's own counts: exact oracle arithmetic on those counts
+        ref_from_counts = ksg_cmi_from_counts(pr.n, pr.k, cnt[0], cnt[1], cnt[2])
+        assert abs(res[i] - ref_from_counts) <= tol(ref_from_counts), i
+        if pr.n <= 4000 and n_full < 6:
+            ref = ksg_cmi(pr.x, pr.y, pr.z, pr.k)
+            assert abs(res[i] - ref) <= tol(ref), i
+            n_full += 1
+    assert n_full >= 3
+
+
+def test_full_size_n10000_parity(lib, ctx):
+    """C1-sized problem (N = 10,000, D = 5) checked in full against the oracle."""
+    p = workloads.random_problem(123, 10000, 1, 1, 3, 4)
+    _check_full(lib, ctx, p.x, p.y, p.z, 4, "n10000")
+
+
+def test_errors(lib, ctx):
+    import torch
+    x = soa(np.zeros((10, 1), np.float32))
+    with pytest.raises(lib.KsgError) as e:
+        ctx.cmi(x, x, None, 10)
+    assert e.value.status == 2
+    with pytest.raises(lib.KsgError) as e:
+        ctx.cmi(x, x, None, 0)
+    assert e.value.status == 1
+    bad = np.ones((50, 1), np.float32)
+    bad[7] = np.nan
+    with pytest.raises(lib.KsgError) as e:
+        ctx.cmi(soa(bad), soa(np.ones((50, 1), np.float32)), None, 4)
+    assert e.value.status == 3
+    big = soa(np.zeros((50, 17), np.float32))
+    with pytest.raises(lib.KsgError) as e:
+        ctx.cmi(big, x, None, 4)
+    assert e.value.status == 1
+    # the context stays usable after errors
+    p = workloads.random_problem(1, 100, 1, 1, 1, 4)
+    ref = ksg_cmi(p.x, p.y, p.z, 4)
+    assert abs(ctx.cmi(soa(p.x), soa(p.y), soa(p.z), 4) - ref) <= tol(ref)
+
+
+def test_deterministic(lib, ctx):
+    p = workloads.random_problem(9, 3000, 1, 1, 4, 4)
+    a = ctx.cmi(soa(p.x), soa(p.y), soa(p.z), 4)
+    b = ctx.cmi(soa(p.x), soa(p.y), soa(p.z), 4)
+    assert a == b
