@@ -110,6 +110,7 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
     for (int i = 0; i <= s.C; ++i)
       cols.push_back(PackJob{cand + (int64_t)i * s.n_pad, nullptr, cand + (int64_t)i * s.n_pad, (int)s.N, (int)s.N});
     KSG_HIP(c, hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+    KSG_HIP(c, launch_perm_check(o->perms, s.P, (int)s.N, c->d_flag, c->stream));
     st = c->check_columns_finite(cols, (int)s.n_pad);
     if (st) return st;
   }

@@ -76,15 +76,15 @@ struct MaxStatOut {
 // Search + count + per-tile digamma partial sums for every work item, then the
 // per-problem finalisation.  kp = number of top-k registers (5, 9 or 17).
 hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
-                             int* d_counter, const double* d_htab, double* d_partials, int shape,
-                             int kp, int grid, hipStream_t stream);
+                             const double* d_htab, double* d_partials, int shape, int kp,
+                             hipStream_t stream);
 hipError_t launch_finalize(const ProbDesc* d_desc, int n_probs, const double* d_partials,
-                           const double* d_htab, double* d_out, int* d_counter, hipStream_t stream);
-int ksg_batch_grid(int shape, int kp, int device_cus);
+                           const double* d_htab, double* d_out, hipStream_t stream);
 
 hipError_t launch_pack(const PackJob* d_jobs, int n_jobs, int max_pad, int* d_flag, hipStream_t stream);
 hipError_t launch_finite_check(const PackJob* d_jobs, int n_jobs, int max_pad, int* d_flag,
                                hipStream_t stream);
+hipError_t launch_perm_check(const int32_t* perms, int n_perm, int n, int* d_flag, hipStream_t stream);
 hipError_t launch_embed(const float* data, int n_vars, int64_t T, int n_trials, int target,
                         int max_lag, float* cand, float* y, int64_t col_stride,
                         hipStream_t stream);

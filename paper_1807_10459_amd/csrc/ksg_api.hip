@@ -403,7 +403,6 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     if (st) return st;
   }
   const int shape = tile_variant >= 0 ? -1 : common_shape;
-  const int grid = ksg_batch_grid(shape, kp, cus);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (timing) {
     t0 = get_event();
@@ -412,8 +411,8 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     KSG_HIP(this, hipEventRecord(t0, stream));
   }
   KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, (const WorkItem*)this->items.ptr,
-                                  (int)items.size(), d_counter, (const double*)htab.ptr,
-                                  (double*)partials.ptr, shape, kp, grid, stream));
+                                  (int)items.size(), (const double*)htab.ptr, (double*)partials.ptr,
+                                  shape, kp, stream));
   if (timing) {
     KSG_HIP(this, hipEventRecord(t1, stream));
     timed.emplace_back(t0, t1);
@@ -421,9 +420,8 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       timed_ops += (double)p.n * (double)(p.n - 1) * (4.0 * (p.dx + p.dy + p.dz) + 2.0);
   }
   KSG_HIP(this, launch_finalize((const ProbDesc*)desc.ptr, np, (const double*)partials.ptr,
-                                (const double*)htab.ptr, d_out, d_counter, stream));
+                                (const double*)htab.ptr, d_out, stream));
   last_items = (int64_t)items.size();
-  last_grid = grid;
   return KSG_OK;
 }
 

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ksg {
@@ -81,6 +83,23 @@ hipError_t launch_finite_check(const PackJob* d_jobs, int n_jobs, int max_pad, i
   return hipGetLastError();
 }
 
+// Sets bit 1 of *flag when any of the n_perm * n gather indices lies outside [0, n).
+__global__ __launch_bounds__(256) void perm_check_kernel(const int32_t* __restrict__ perms, int64_t total,
+                                                         int n, int* __restrict__ flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+    bad |= (unsigned)perms[i] >= (unsigned)n;
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 2);
+}
+
+hipError_t launch_perm_check(const int32_t* perms, int n_perm, int n, int* d_flag, hipStream_t stream) {
+  const int64_t total = (int64_t)n_perm * n;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(perm_check_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, perms, total, n, d_flag);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ embedding
 
 // Candidate (v, l) row i: trial tr = i / (T - L), time t = L + i % (T - L), value x_v(t - l).
@@ -118,14 +137,12 @@ hipError_t launch_embed(const float* data, int n_vars, int64_t T, int n_trials, 
 // ------------------------------------------------------------------ finalisation
 
 // I = H_{k-1} - S / N, S = compensated (Neumaier) sum of the problem's tile partials in tile
-// order.  Thread 0 also re-arms the work counter of the search kernel for the next launch.
+// order.
 __global__ __launch_bounds__(256) void finalize_kernel(const ProbDesc* __restrict__ descs, int n_probs,
                                                        const double* __restrict__ partials,
                                                        const double* __restrict__ htab,
-                                                       double* __restrict__ out,
-                                                       int* __restrict__ counter) {
+                                                       double* __restrict__ out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p == 0) *counter = 0;
   if (p >= n_probs) return;
   const ProbDesc& d = descs[p];
   double s = 0.0, comp = 0.0;
@@ -145,35 +162,23 @@ static const void* pick_search_kernel(int shape, int kp) {
   return table[39];
 }
 
-int ksg_batch_grid(int shape, int kp, int device_cus) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pick_search_kernel(shape, kp), kTileQ, 0) !=
-          hipSuccess ||
-      per_cu <= 0)
-    per_cu = 1;
-  return per_cu * device_cus;
-}
-
 hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
-                             int* d_counter, const double* d_htab, double* d_partials, int shape,
-                             int kp, int grid, hipStream_t stream) {
+                             const double* d_htab, double* d_partials, int shape, int kp,
+                             hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
   const void* fn = pick_search_kernel(shape, kp);
   const ProbDesc* a0 = d_desc;
   const WorkItem* a1 = d_items;
-  int a2 = n_items;
-  int* a3 = d_counter;
-  const double* a4 = d_htab;
-  double* a5 = d_partials;
-  void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5};
-  const int g = grid < n_items ? grid : n_items;
-  return hipLaunchKernel(fn, dim3(g), dim3(kTileQ), args, 0, stream);
+  const double* a2 = d_htab;
+  double* a3 = d_partials;
+  void* args[] = {&a0, &a1, &a2, &a3};
+  return hipLaunchKernel(fn, dim3(n_items), dim3(kTileQ), args, 0, stream);
 }
 
 hipError_t launch_finalize(const ProbDesc* d_desc, int n_probs, const double* d_partials,
-                           const double* d_htab, double* d_out, int* d_counter, hipStream_t stream) {
+                           const double* d_htab, double* d_out, hipStream_t stream) {
   hipLaunchKernelGGL(finalize_kernel, dim3((n_probs + 255) / 256), dim3(256), 0, stream, d_desc,
-                     n_probs, d_partials, d_htab, d_out, d_counter);
+                     n_probs, d_partials, d_htab, d_out);
   return hipGetLastError();
 }
 

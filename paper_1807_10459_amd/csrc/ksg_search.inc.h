@@ -268,45 +268,39 @@ __device__ __forceinline__ void dispatch_generic(int D, const KSG_AS4 ProbDesc* 
   }
 }
 
-// Persistent batched kernel.  SHAPE >= 0: every problem of the launch has that fast shape;
-// SHAPE == -1: mixed batch, per-problem dispatch.  Work items are claimed with one atomic per
-// item from a counter that the finalisation kernel resets to zero.
+// Batched kernel: one work-group per work item (problem, 256-query tile).  The host orders
+// the items longest-problem-first and the hardware dispatcher hands work-groups to compute
+// units in that order as they free up, which gives the dynamic longest-first schedule of a
+// work queue without a device-side queue.  SHAPE >= 0: every problem of the launch has that
+// fast shape; SHAPE == -1: mixed batch, per-problem dispatch.
 template <int SHAPE, int KP>
 __global__ __launch_bounds__(kTileQ) void ksg_batch_kernel(const ProbDesc* __restrict__ descs,
                                                            const WorkItem* __restrict__ items,
-                                                           int n_items, int* __restrict__ counter,
                                                            const double* __restrict__ htab,
                                                            double* __restrict__ partials) {
-  __shared__ int s_item;
   __shared__ double s_red[kTileQ / 64];
   const KSG_AS4 ProbDesc* d4 = (const KSG_AS4 ProbDesc*)descs;
   const KSG_AS4 WorkItem* i4 = (const KSG_AS4 WorkItem*)items;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(s_item);
-    __syncthreads();
-    if (it >= n_items) break;
-    const int prob = i4[it].prob;
-    const int tile = i4[it].tile;
-    const KSG_AS4 ProbDesc* pd = d4 + prob;
-    if constexpr (SHAPE >= 0 && SHAPE < kGenericShape) {
-      constexpr int PAIR = SHAPE / (kFastMaxDz + 1);
-      constexpr int DZ = SHAPE % (kFastMaxDz + 1);
-      constexpr int DX = PAIR == 2 ? 2 : 1;
-      constexpr int DY = PAIR == 0 ? 1 : 2;
-      search_tile<DX, DY, DZ, KP, ((DX + DY + DZ) <= 8 ? 8 : 4)>(pd, tile, htab, partials, s_red);
+  const int it = blockIdx.x;
+  const int prob = i4[it].prob;
+  const int tile = i4[it].tile;
+  const KSG_AS4 ProbDesc* pd = d4 + prob;
+  if constexpr (SHAPE >= 0 && SHAPE < kGenericShape) {
+    constexpr int PAIR = SHAPE / (kFastMaxDz + 1);
+    constexpr int DZ = SHAPE % (kFastMaxDz + 1);
+    constexpr int DX = PAIR == 2 ? 2 : 1;
+    constexpr int DY = PAIR == 0 ? 1 : 2;
+    search_tile<DX, DY, DZ, KP, ((DX + DY + DZ) <= 8 ? 8 : 4)>(pd, tile, htab, partials, s_red);
+  } else {
+    const int shape = pd->variant;
+    if (shape >= kGenericShape) {
+      dispatch_generic<KP>(pd->dx + pd->dy + pd->dz, pd, tile, htab, partials, s_red);
     } else {
-      const int shape = pd->variant;
-      if (shape >= kGenericShape) {
-        dispatch_generic<KP>(pd->dx + pd->dy + pd->dz, pd, tile, htab, partials, s_red);
-      } else {
-        switch (shape) {
-          KSG_FAST_PAIR(0, 1, 1)
-          KSG_FAST_PAIR(1, 1, 2)
-          KSG_FAST_PAIR(2, 2, 2)
-          default: break;
-        }
+      switch (shape) {
+        KSG_FAST_PAIR(0, 1, 1)
+        KSG_FAST_PAIR(1, 1, 2)
+        KSG_FAST_PAIR(2, 2, 2)
+        default: break;
       }
     }
   }

@@ -50,7 +50,7 @@ struct ksg_ctx {
 
   ksg::DevBuf htab, pool, desc, items, partials, jobs, tmp, embed, cmi, aux, feat;
   int64_t htab_n = 0;
-  int* d_counter = nullptr;  // [0]: search work counter, [1]: finite flag
+  int* d_counter = nullptr;  // [1]: finite / permutation-range flag
   int* d_flag = nullptr;
   ksg::MaxStatOut* d_ms = nullptr;
   ksg::MaxStatOut* h_ms = nullptr;  // pinned
@@ -61,7 +61,6 @@ struct ksg_ctx {
   bool staging_pending = false;
 
   int64_t last_items = 0;
-  int last_grid = 0;
 
   // KSG_OPT_TIMING: events around each search launch, harvested by ksg_take_timing.
   bool timing = false;

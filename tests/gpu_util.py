@@ -13,6 +13,8 @@ def dev(a, dtype=None):
 def soa(points):
     """Row-major [N][d] float32 points -> device SoA [d][N] float32 (None for d == 0)."""
     import torch
+    if points is None:
+        return None
     p = np.asarray(points, dtype=np.float32)
     if p.ndim == 1:
         p = p[:, None]

@@ -1,0 +1,129 @@
+"""Parity of the embedding, max-statistic, greedy-step and select_parents entry points with
+the CPU oracle (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle.ksg import ksg_cmi
+from oracle.stats import embed, greedy_select, max_statistic, omnibus_test
+from tests.gpu_util import dev, tol
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.Context(0)
+    yield c
+    c.close()
+
+
+def test_embed_matches_oracle(lib, ctx):
+    net = workloads.logistic_network(seed=3, n_nodes=6, n_trials=3, T=300)
+    cand, y = ctx.embed(dev(net.data), target=2, max_lag=5)
+    rc, ry = embed(net.data, target=2, max_lag=5)
+    assert np.array_equal(cand.cpu().numpy(), rc)
+    assert np.array_equal(y.cpu().numpy(), ry)
+
+
+@pytest.mark.parametrize("c,P", [(1, 1), (1, 200), (7, 19), (25, 200), (100, 500), (3, 4096)])
+def test_maxstat_matches_oracle(lib, ctx, c, P):
+    g = workloads.rng(c * 1000 + P)
+    t = np.round(g.standard_normal((c, P + 1)), 2)  # coarse values: ties in originals and maxima
+    r = ctx.maxstat(dev(t), alpha=0.05)
+    o = max_statistic(t, 0.05)
+    assert r["c_star"] == o.c_star and r["count"] == o.count
+    assert r["t_obs"] == o.t_obs and r["pval"] == o.pval and r["significant"] == o.significant
+    assert r["tau05"] == o.tau05 and r["tau01"] == o.tau01
+
+
+def test_maxstat_rejects_bad_sizes(lib, ctx):
+    with pytest.raises(lib.KsgError):
+        ctx.maxstat(dev(np.zeros((2, 4098))), 0.05)
+    with pytest.raises(lib.KsgError):
+        ctx.maxstat(dev(np.zeros((2, 5))), 1.5)
+
+
+def _small_chain(seed, n_vars=4, T=260, n_trials=2):
+    """y (last variable) driven by var 1 at lag 1 and var 2 at lag 2; others noise."""
+    g = workloads.rng(seed)
+    x = g.standard_normal((n_trials, n_vars, T))
+    for tr in range(n_trials):
+        for t in range(2, T):
+            x[tr, -1, t] = 0.8 * x[tr, 1, t - 1] + 0.6 * x[tr, 2, t - 2] + 0.4 * g.standard_normal()
+    return x.astype(np.float32)
+
+
+def test_greedy_step_matches_oracle(lib, ctx):
+    data = _small_chain(21)
+    cand, y = embed(data, target=3, max_lag=2)
+    perms = workloads.permutations(y.size, 19, seed=22)
+    pool, cond = [0, 1, 2, 4, 5, 7], [3, 6]
+    tab, r = ctx.greedy_step(dev(cand), dev(y), pool, cond, dev(perms), k=4)
+    tab = tab.cpu().numpy()
+    z = np.stack([cand[c] for c in cond], 1)
+    for ci, c in enumerate(pool):
+        for p in (0, 1, 19):
+            x = cand[c] if p == 0 else cand[c][perms[p - 1]]
+            ref = ksg_cmi(x, y, z, 4)
+            assert abs(tab[ci, p] - ref) <= tol(ref), (c, p)
+    o = max_statistic(tab, 0.05)
+    assert r["c_star"] == o.c_star and r["count"] == o.count and r["significant"] == o.significant
+
+
+def test_select_parents_matches_oracle(lib, ctx):
+    data = _small_chain(31)
+    L, P = 2, 19
+    cand, y = embed(data, target=3, max_lag=L)
+    perms = workloads.permutations(y.size, P, seed=32)
+    sel, steps = greedy_select(cand, y, 4, perms, alpha=0.05)
+    r = ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=L, alpha=0.05, omnibus=True)
+    assert r["candidates"] == sel
+    assert r["n_steps"] == len(steps)
+    for i, s in enumerate(steps[:len(sel)]):
+        assert abs(r["cmi"][i] - s.t_obs) <= tol(s.t_obs)
+        assert r["pval"][i] == s.pval
+    assert r["n_cmi"] == sum((cand.shape[0] - i) * (P + 1) for i in range(len(steps))) + (P + 1) * r["omnibus_tested"]
+    om = omnibus_test(cand, y, sel, target=3, max_lag=L, k=4, perms=perms)
+    if om is None:
+        assert not r["omnibus_tested"]
+    else:
+        assert r["omnibus_tested"] and r["omnibus_significant"] == om[1].significant
+        assert abs(r["omnibus_cmi"] - om[1].t_obs) <= tol(om[1].t_obs)
+        assert r["omnibus_pval"] == om[1].pval
+
+
+def test_select_parents_max_steps_and_capacity(lib, ctx):
+    data = _small_chain(41)
+    perms = workloads.permutations(2 * 258, 9, seed=42)
+    r = ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=2, max_steps=1)
+    assert r["n_steps"] == 1
+    with pytest.raises(lib.KsgError) as e:
+        ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=2, capacity=0)
+    assert e.value.status == 7
+
+
+def test_select_parents_bad_permutation_rejected(lib, ctx):
+    data = _small_chain(51)
+    perms = workloads.permutations(2 * 258, 3, seed=52)
+    perms[1, 7] = 10 ** 6  # outside [0, N)
+    with pytest.raises(lib.KsgError) as e:
+        ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=2)
+    assert e.value.status == 1
+    # the context stays usable
+    perms[1, 7] = 7
+    ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=2, max_steps=1)
+
+
+def test_ar2_full_size_recovers_true_parents(lib, ctx):
+    """Full-size AR(2) workload (N = 10,000, 25 candidates, 200 surrogates): the greedy run
+    must include every true source parent and the target's own lag-1 and lag-2 past."""
+    net = workloads.ar2_network(seed=1)
+    perms = workloads.permutations(10000, 200, seed=11)
+    r = ctx.select_parents(dev(net.data), target=0, perms=dev(perms), k=4, max_lag=5)
+    got = set(r["parents"])
+    want = {(src, lag) for (src, _, lag) in net.edges} | {(0, 1), (0, 2)}
+    assert want <= got, (sorted(got), sorted(want))
+    assert len(got) <= len(want) + 2  # few false positives at alpha = 0.05
+    # the steps' p-values of included parents are below alpha
+    assert all(p < 0.05 for p in r["pval"])
