@@ -10,9 +10,11 @@ strict range counts, FP64 digamma sums) and the max-statistic test.  That is 32,
 estimates per step.  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line.  The roofline object is for the search kernel: algorithmic FP32
-operations N(N-1)(4D+2) per CMI over its HIP-event time, against the FP32 VALU lane-op
-peak 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.32 T/s.  cpu_baseline times the CPU oracle
-on a sample of the same CMIs.
+operations N(N-1)(4D+2) per CMI over its HIP-event time, against the FP32 VALU peak for
+operations that are not fused multiply-adds: the 157.3 TFLOP/s FP32 vector figure counts an
+FMA as two operations, so 78.6 T FP32 lane-operations per second (256 CUs x 4 SIMDs x 32
+FP32 lanes per clock x 2.4 GHz).  cpu_baseline times the CPU oracle on a sample of the same
+CMIs.
 """
 from __future__ import annotations
 
@@ -28,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_VALU = 256 * 4 * 16 * 2.4e9  # FP32 lane-operations per second (non-packed, non-FMA)
+PEAK_VALU = 157.3e12 / 2  # FP32 lane-operations per second that are not FMAs
 N_PERM = 200
 MAX_LAG = 5
 K = 4
@@ -84,6 +86,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (a known-size kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
@@ -164,6 +168,15 @@ def main():
                    "n_cmi_per_step": n_cmi},
         "roofline": roofline,
     }
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
+        del src, dst
 
     if not args.no_cpu_baseline:
         cand_np = cand.cpu().numpy()
