@@ -92,7 +92,9 @@ const char* ksg_last_error(const ksg_ctx* ctx);
 /* Options. */
 typedef enum ksg_option {
   KSG_OPT_CHECK_FINITE = 1, /* 1 (default): reject non-finite data; 0: trust inputs */
-  KSG_OPT_TILE_VARIANT = 2, /* -1 (default): autotuned tile variant; >= 0 forces one */
+  KSG_OPT_GROUP_SIZE = 2,   /* problems searched together when they share Y, Z, N and k and
+                               have 1-D X: -1 (default) = autotuned per conditioning dimension,
+                               0 = off, 8 or 16 = forced */
   KSG_OPT_USE_GRAPH = 3,    /* 1 (default): replay greedy steps from a captured hipGraph */
   KSG_OPT_TIMING = 4        /* 1: time every search-kernel launch with HIP events (default 0) */
 } ksg_option;

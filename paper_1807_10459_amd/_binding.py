@@ -164,7 +164,7 @@ class Context:
     """A library context on one device, issuing work on the current torch stream."""
 
     OPT_CHECK_FINITE = 1
-    OPT_TILE_VARIANT = 2
+    OPT_GROUP_SIZE = 2
     OPT_USE_GRAPH = 3
     OPT_TIMING = 4
 

@@ -15,6 +15,10 @@ SOURCES = [
     "ksg_search_kp5.hip",
     "ksg_search_kp9.hip",
     "ksg_search_kp17.hip",
+    "ksg_group_kp5_g8.hip",
+    "ksg_group_kp5_g16.hip",
+    "ksg_group_kp9_g8.hip",
+    "ksg_group_kp9_g16.hip",
     "ksg_misc.hip",
     "ksg_api.hip",
     "greedy.hip",

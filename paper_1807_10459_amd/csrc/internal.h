@@ -29,7 +29,22 @@ struct alignas(16) ProbDesc {
   int32_t pad_[3];
 };
 
-// Work item: one query tile of one problem.
+// G problems that share Y (1-D), Z (m columns), N and k and differ in a 1-D X column.
+// Column data live in one pool; offsets are in floats.  Problem g of the group writes its
+// per-tile partial sums at part_base + g * n_tiles + tile.
+constexpr int kGroupMax = 16;
+struct alignas(16) GroupDesc {
+  uint32_t x_off[kGroupMax];
+  uint32_t y_off;
+  uint32_t z_off[kMaxDims - 2];
+  int32_t n, n_pad, k, m;
+  int32_t ng;         // problems in this group (the rest of x_off repeats a valid column)
+  int32_t n_tiles;
+  int32_t part_base;
+  int32_t pad_[2];
+};
+
+// Work item: one query tile of one problem (or group); prob < 0 marks an empty slot.
 struct WorkItem {
   int32_t prob;
   int32_t tile;
@@ -78,6 +93,9 @@ struct MaxStatOut {
 hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                              const double* d_htab, double* d_partials, int shape, int kp,
                              hipStream_t stream);
+hipError_t launch_ksg_group(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
+                            int n_items, const double* d_htab, double* d_partials, int m, int G,
+                            int kp, hipStream_t stream);
 hipError_t launch_finalize(const ProbDesc* d_desc, int n_probs, const double* d_partials,
                            const double* d_htab, double* d_out, hipStream_t stream);
 

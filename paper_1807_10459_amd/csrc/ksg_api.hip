@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
 #include <unordered_map>
 #include <vector>
 
@@ -218,7 +219,11 @@ extern "C" int ksg_ctx_set_option(ksg_ctx* c, int option, int64_t value) {
   if (!c) return KSG_EINVAL;
   switch (option) {
     case KSG_OPT_CHECK_FINITE: c->check_finite = value != 0; return KSG_OK;
-    case KSG_OPT_TILE_VARIANT: c->tile_variant = (int)value; return KSG_OK;
+    case KSG_OPT_GROUP_SIZE:
+      if (value != -1 && value != 0 && value != 8 && value != 16)
+        return c->fail(KSG_EINVAL, "group size must be -1 (tuned), 0 (off), 8 or 16");
+      c->group_size = (int)value;
+      return KSG_OK;
     case KSG_OPT_USE_GRAPH: c->use_graph = value != 0; return KSG_OK;
     case KSG_OPT_TIMING: c->timing = value != 0; return KSG_OK;
     default: return c->fail(KSG_EINVAL, "unknown option %d", option);
@@ -245,6 +250,57 @@ int ksg_ctx::validate(const Problem& p, int index) {
   return KSG_OK;
 }
 
+namespace {
+
+// A unit of scheduling: one problem (ungrouped) or one group, with all its tiles.
+struct Unit {
+  int id;
+  int n_tiles;
+  double cost;
+};
+
+// Work items for a list of units (already in longest-first order).  With many units, each
+// unit goes whole to one of the 8 XCDs (least-loaded first) and the items are interleaved
+// so that work-group b, which the dispatcher places on XCD b % 8, takes the next item of
+// that XCD's list: a problem's columns are then read into one XCD's L2 only.  Empty slots
+// (prob = -1) return at once.  With few units the plain order keeps every XCD busy.
+std::vector<WorkItem> order_items(const std::vector<Unit>& units) {
+  constexpr int kXcd = 8;
+  std::vector<WorkItem> out;
+  if ((int)units.size() < 4 * kXcd) {
+    for (const Unit& u : units)
+      for (int t = 0; t < u.n_tiles; ++t) out.push_back(WorkItem{u.id, t});
+    return out;
+  }
+  std::vector<std::vector<WorkItem>> bins(kXcd);
+  std::vector<double> load(kXcd, 0.0);
+  for (const Unit& u : units) {
+    int x = 0;
+    for (int i = 1; i < kXcd; ++i)
+      if (load[i] < load[x]) x = i;
+    load[x] += u.cost;
+    for (int t = 0; t < u.n_tiles; ++t) bins[x].push_back(WorkItem{u.id, t});
+  }
+  size_t L = 0;
+  for (auto& b : bins) L = std::max(L, b.size());
+  out.assign(L * kXcd, WorkItem{-1, 0});
+  for (int x = 0; x < kXcd; ++x)
+    for (size_t s = 0; s < bins[x].size(); ++s) out[s * kXcd + x] = bins[x][s];
+  return out;
+}
+
+}  // namespace
+
+// Problems that share Y, Z, N and k and differ only in a 1-D X column can be searched as a
+// group (Y/Z distances computed once per pair for the whole group).
+static bool groupable(const Problem& p) {
+  if (p.dx != 1 || p.dy != 1 || p.dz > kMaxDims - 2 || p.k + 1 > 9) return false;
+  if (p.eps_out || p.counts_out || p.local_out) return false;
+  for (int a = 1; a < 2 + p.dz; ++a)
+    if (p.perm[a]) return false;
+  return true;
+}
+
 int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   const int np = (int)probs.size();
   if (np == 0) return KSG_OK;
@@ -257,7 +313,35 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   int st = ensure_htab(nmax);
   if (st) return st;
 
+  // ---- grouping: problems with identical (N, k, Y, Z) and 1-D X ----
+  std::vector<int> group_of(np, -1);
+  std::vector<std::vector<int>> groups;  // member problem indices
+  std::vector<int> group_size_of;        // G of each group's kernel
+  if (group_size != 0) {
+    std::map<std::vector<intptr_t>, std::vector<int>> by_key;
+    for (int i = 0; i < np; ++i) {
+      const Problem& p = probs[i];
+      if (!groupable(p)) continue;
+      std::vector<intptr_t> key = {(intptr_t)p.n, p.k, p.dz, (intptr_t)p.col[1]};
+      for (int a = 0; a < p.dz; ++a) key.push_back((intptr_t)p.col[2 + a]);
+      by_key[key].push_back(i);
+    }
+    for (auto& kv : by_key) {
+      const std::vector<int>& members = kv.second;
+      if (members.size() < 2) continue;
+      const int m = probs[members[0]].dz;
+      const int G = group_size > 0 ? group_size : tuned_group_size(m, probs[members[0]].k);
+      for (size_t s = 0; s < members.size(); s += G) {
+        std::vector<int> g(members.begin() + s, members.begin() + std::min(members.size(), s + (size_t)G));
+        for (int i : g) group_of[i] = (int)groups.size();
+        groups.push_back(g);
+        group_size_of.push_back(G);
+      }
+    }
+  }
+
   // ---- column pool: pack every column that is not already a padded device column ----
+  // Grouped problems address all their columns through one pool, so they always pack.
   struct Key {
     const float* src;
     const int32_t* perm;
@@ -273,7 +357,6 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   std::vector<PackJob> jobs;
   int64_t pool_floats = 0;
   int max_pad = 0;
-  // First pass: assign pool offsets (as integers; converted to pointers once the pool exists).
   std::vector<std::array<int64_t, kMaxDims>> col_off(np);
   for (int i = 0; i < np; ++i) {
     const Problem& p = probs[i];
@@ -281,7 +364,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     const int64_t n_pad = round_up(p.n, kPad);
     max_pad = std::max<int>(max_pad, (int)n_pad);
     for (int a = 0; a < D; ++a) {
-      if (p.padded[a] && !p.perm[a]) {
+      if (p.padded[a] && !p.perm[a] && group_of[i] < 0) {
         col_off[i][a] = -1;  // used in place
         continue;
       }
@@ -301,42 +384,49 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       col_off[i][a] = it->second;
     }
   }
+  if (!groups.empty() && pool_floats > (int64_t)UINT32_MAX)
+    return fail(KSG_ENOMEM, "batch needs %lld pool floats, above the 2^32 addressable by groups",
+                (long long)pool_floats);
   st = reserve(pool, sizeof(float) * std::max<int64_t>(pool_floats, 1), "column pool");
   if (st) return st;
   float* pool_base = static_cast<float*>(pool.ptr);
   for (PackJob& j : jobs) j.dst = pool_base + reinterpret_cast<int64_t>(j.dst);
 
-  // ---- descriptors (longest-processing-time first) and work items ----
-  std::vector<int> order(np);
-  for (int i = 0; i < np; ++i) order[i] = i;
   auto cost = [&](int i) {
     const Problem& p = probs[i];
     return (double)p.n * (double)p.n * (4.0 * (p.dx + p.dy + p.dz) + 2.0);
   };
+  auto n_tiles_of = [&](int i) { return (int)((probs[i].n + kTileQ - 1) / kTileQ); };
+
+  // ---- per-problem descriptors (search of ungrouped problems + finalisation of all) ----
+  std::vector<int> order;
+  for (int i = 0; i < np; ++i) order.push_back(i);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
   std::vector<ProbDesc> descs(np);
-  std::vector<WorkItem> items;
+  std::vector<int> desc_of(np);
   int part = 0;
+  // Group partial slots first (contiguous per group), then ungrouped problems.
+  std::vector<int> group_part(groups.size());
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    group_part[gi] = part;
+    part += (int)groups[gi].size() * n_tiles_of(groups[gi][0]);
+  }
   int common_shape = -2;
   int kp = 5;
-  for (int i = 0; i < np; ++i) {
-    const Problem& p = probs[i];
-    kp = std::max(kp, p.k + 1 <= 5 ? 5 : (p.k + 1 <= 9 ? 9 : 17));
-  }
   for (int r = 0; r < np; ++r) {
     const int i = order[r];
     const Problem& p = probs[i];
+    desc_of[i] = r;
     ProbDesc& d = descs[r];
     std::memset(&d, 0, sizeof d);
     const bool swap = p.dx > p.dy;
     const int dx = swap ? p.dy : p.dx, dy = swap ? p.dx : p.dy;
     const int D = p.dx + p.dy + p.dz;
-    // source dimension for each canonical slot
     for (int a = 0; a < D; ++a) {
       int src = a;
       if (swap) {
-        if (a < dx) src = p.dx + a;            // canonical X = original Y
-        else if (a < dx + dy) src = a - dx;    // canonical Y = original X
+        if (a < dx) src = p.dx + a;          // canonical X = original Y
+        else if (a < dx + dy) src = a - dx;  // canonical Y = original X
       }
       d.col[a] = col_off[i][src] < 0 ? p.col[src] : pool_base + col_off[i][src];
     }
@@ -346,41 +436,96 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     d.dy = dy;
     d.dz = p.dz;
     d.k = p.k;
-    d.n_tiles = (int)((p.n + kTileQ - 1) / kTileQ);
-    d.part_base = part;
+    d.n_tiles = n_tiles_of(i);
     d.eps_out = p.eps_out;
     d.counts_out = p.counts_out;
     d.local_out = p.local_out;
     d.variant = shape_id(dx, dy, p.dz);
     d.out_index = p.out_index;
     d.swap_xy = swap ? 1 : 0;
-    for (int t = 0; t < d.n_tiles; ++t) items.push_back(WorkItem{r, t});
-    part += d.n_tiles;
-    if (common_shape == -2) common_shape = d.variant;
-    else if (common_shape != d.variant) common_shape = -1;
+    if (group_of[i] >= 0) {
+      const int gi = group_of[i];
+      const int g = (int)(std::find(groups[gi].begin(), groups[gi].end(), i) - groups[gi].begin());
+      d.part_base = group_part[gi] + g * d.n_tiles;
+    } else {
+      d.part_base = part;
+      part += d.n_tiles;
+      kp = std::max(kp, p.k + 1 <= 5 ? 5 : (p.k + 1 <= 9 ? 9 : 17));
+      if (common_shape == -2) common_shape = d.variant;
+      else if (common_shape != d.variant) common_shape = -1;
+    }
   }
   if (common_shape >= kGenericShape) common_shape = -1;
 
-  // ---- upload: one pinned staging block, one copy ----
+  // ungrouped work items
+  std::vector<Unit> units;
+  for (int r = 0; r < np; ++r)
+    if (group_of[order[r]] < 0) units.push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
+  std::vector<WorkItem> items = order_items(units);
+
+  // group descriptors and items, one launch per (m, G, KP) class
+  std::vector<GroupDesc> gdescs(groups.size());
+  std::map<std::array<int, 3>, std::vector<Unit>> classes;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Problem& p0 = probs[groups[gi][0]];
+    GroupDesc& gd = gdescs[gi];
+    std::memset(&gd, 0, sizeof gd);
+    const int i0 = groups[gi][0];
+    for (int g = 0; g < kGroupMax; ++g) {
+      const int i = groups[gi][g < (int)groups[gi].size() ? g : 0];
+      gd.x_off[g] = (uint32_t)col_off[i][0];
+    }
+    gd.y_off = (uint32_t)col_off[i0][1];
+    for (int a = 0; a < p0.dz; ++a) gd.z_off[a] = (uint32_t)col_off[i0][2 + a];
+    gd.n = (int)p0.n;
+    gd.n_pad = (int)round_up(p0.n, kPad);
+    gd.k = p0.k;
+    gd.m = p0.dz;
+    gd.ng = (int)groups[gi].size();
+    gd.n_tiles = n_tiles_of(i0);
+    gd.part_base = group_part[gi];
+    const int gkp = p0.k + 1 <= 5 ? 5 : 9;
+    classes[{p0.dz, group_size_of[gi], gkp}].push_back(
+        Unit{(int)gi, gd.n_tiles, cost(i0) * gd.ng});
+  }
+  std::vector<std::vector<WorkItem>> group_items;
+  for (auto& kv : classes) {
+    std::stable_sort(kv.second.begin(), kv.second.end(),
+                     [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
+    group_items.push_back(order_items(kv.second));
+  }
+
+  // ---- upload: one pinned staging block, one copy per array ----
+  size_t n_gitems = 0;
+  for (auto& v : group_items) n_gitems += v.size();
   const size_t sz_desc = sizeof(ProbDesc) * np;
-  const size_t sz_items = sizeof(WorkItem) * items.size();
+  const size_t sz_items = sizeof(WorkItem) * (items.size() + n_gitems);
   const size_t sz_jobs = sizeof(PackJob) * jobs.size();
-  st = reserve_host(sz_desc + sz_items + sz_jobs + 64);
+  const size_t sz_g = sizeof(GroupDesc) * gdescs.size();
+  st = reserve_host(sz_desc + sz_items + sz_jobs + sz_g + 64);
   if (st) return st;
-  st = reserve(desc, sz_desc, "descriptors");
-  if (!st) st = reserve(this->items, sz_items, "work items");
+  st = reserve(desc, sz_desc + sz_g, "descriptors");
+  if (!st) st = reserve(this->items, std::max<size_t>(sz_items, 16), "work items");
   if (!st) st = reserve(this->jobs, std::max<size_t>(sz_jobs, 16), "pack jobs");
   if (!st) st = reserve(partials, sizeof(double) * std::max(part, 1), "partial sums");
   if (st) return st;
   char* h = static_cast<char*>(staging);
   std::memcpy(h, descs.data(), sz_desc);
-  std::memcpy(h + sz_desc, items.data(), sz_items);
-  if (sz_jobs) std::memcpy(h + sz_desc + sz_items, jobs.data(), sz_jobs);
-  KSG_HIP(this, hipMemcpyAsync(desc.ptr, h, sz_desc, hipMemcpyHostToDevice, stream));
-  KSG_HIP(this, hipMemcpyAsync(this->items.ptr, h + sz_desc, sz_items, hipMemcpyHostToDevice, stream));
-  if (sz_jobs)
-    KSG_HIP(this, hipMemcpyAsync(this->jobs.ptr, h + sz_desc + sz_items, sz_jobs,
-                                 hipMemcpyHostToDevice, stream));
+  if (sz_g) std::memcpy(h + sz_desc, gdescs.data(), sz_g);
+  char* hi = h + sz_desc + sz_g;
+  if (!items.empty()) std::memcpy(hi, items.data(), sizeof(WorkItem) * items.size());
+  size_t off = items.size();
+  std::vector<size_t> gitem_off;
+  for (auto& v : group_items) {
+    gitem_off.push_back(off);
+    std::memcpy(hi + sizeof(WorkItem) * off, v.data(), sizeof(WorkItem) * v.size());
+    off += v.size();
+  }
+  char* hj = hi + sz_items;
+  if (sz_jobs) std::memcpy(hj, jobs.data(), sz_jobs);
+  KSG_HIP(this, hipMemcpyAsync(desc.ptr, h, sz_desc + sz_g, hipMemcpyHostToDevice, stream));
+  if (sz_items) KSG_HIP(this, hipMemcpyAsync(this->items.ptr, hi, sz_items, hipMemcpyHostToDevice, stream));
+  if (sz_jobs) KSG_HIP(this, hipMemcpyAsync(this->jobs.ptr, hj, sz_jobs, hipMemcpyHostToDevice, stream));
   KSG_HIP(this, hipEventRecord(staging_done, stream));
   staging_pending = true;
 
@@ -391,18 +536,16 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   }
   if (check_finite) {
     // In-place columns are checked through identity jobs over their first n rows.
-    std::vector<PackJob> inplace;
+    std::vector<PackJob> all = jobs;
     for (int i = 0; i < np; ++i) {
       const Problem& p = probs[i];
       for (int a = 0; a < p.dx + p.dy + p.dz; ++a)
-        if (col_off[i][a] < 0) inplace.push_back(PackJob{p.col[a], nullptr, const_cast<float*>(p.col[a]), (int)p.n, (int)p.n});
+        if (col_off[i][a] < 0)
+          all.push_back(PackJob{p.col[a], nullptr, const_cast<float*>(p.col[a]), (int)p.n, (int)p.n});
     }
-    std::vector<PackJob> all = jobs;
-    all.insert(all.end(), inplace.begin(), inplace.end());
     st = check_columns_finite(all, max_pad);
     if (st) return st;
   }
-  const int shape = tile_variant >= 0 ? -1 : common_shape;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (timing) {
     t0 = get_event();
@@ -410,19 +553,46 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     if (!t0 || !t1) return fail(KSG_EDEVICE, "cannot create timing events");
     KSG_HIP(this, hipEventRecord(t0, stream));
   }
-  KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, (const WorkItem*)this->items.ptr,
-                                  (int)items.size(), (const double*)htab.ptr, (double*)partials.ptr,
-                                  shape, kp, stream));
+  const WorkItem* d_items = (const WorkItem*)this->items.ptr;
+  const GroupDesc* d_gdesc = (const GroupDesc*)((char*)desc.ptr + sz_desc);
+  {
+    size_t ci = 0;
+    for (auto& kv : classes) {
+      KSG_HIP(this, launch_ksg_group(pool_base, d_gdesc, d_items + gitem_off[ci], (int)group_items[ci].size(),
+                                     (const double*)htab.ptr, (double*)partials.ptr, kv.first[0],
+                                     kv.first[1], kv.first[2], stream));
+      ++ci;
+    }
+  }
+  if (!items.empty()) {
+    const int shape = common_shape;
+    KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items, (int)items.size(),
+                                    (const double*)htab.ptr, (double*)partials.ptr, shape, kp, stream));
+  }
   if (timing) {
     KSG_HIP(this, hipEventRecord(t1, stream));
     timed.emplace_back(t0, t1);
-    for (const Problem& p : probs)
-      timed_ops += (double)p.n * (double)(p.n - 1) * (4.0 * (p.dx + p.dy + p.dz) + 2.0);
+    for (int i = 0; i < np; ++i) timed_ops += algorithmic_ops(probs[i], group_of[i] >= 0 ? (int)groups[group_of[i]].size() : 1);
   }
   KSG_HIP(this, launch_finalize((const ProbDesc*)desc.ptr, np, (const double*)partials.ptr,
                                 (const double*)htab.ptr, d_out, stream));
-  last_items = (int64_t)items.size();
+  last_items = (int64_t)(items.size() + n_gitems);
+  last_groups = (int64_t)groups.size();
   return KSG_OK;
+}
+
+// Algorithmic FP32 operations of one problem.  Ungrouped: the brute-force count over ordered
+// pairs, N(N-1)(4D+2) (radius: D sub, D-1 max, 1 compare; counts: D sub, D-1 max, 3 compares).
+// In a group of ng problems that share Y and Z, the Y/Z part of both passes is done once per
+// pair for the group, so each problem carries 1/ng of it: per pair, radius 1 sub + 1 max + 1
+// compare and counts 1 sub + 1 max + 3 compares per problem, plus (2(m+1) - 1) + (2(m+1) - 1)
+// shared sub/max operations (d^YZ for the radius; d^Z and d^YZ for the counts) divided by ng.
+double ksg_ctx::algorithmic_ops(const Problem& p, int ng) {
+  const double pairs = (double)p.n * (double)(p.n - 1);
+  const int D = p.dx + p.dy + p.dz;
+  if (ng <= 1) return pairs * (4.0 * D + 2.0);
+  const double shared = 2.0 * (2.0 * (p.dz + 1) - 1.0);
+  return pairs * (8.0 + shared / ng);
 }
 
 // Finite check over the destinations (first n rows) of the given jobs; synchronises.

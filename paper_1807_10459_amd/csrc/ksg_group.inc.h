@@ -1,0 +1,183 @@
+// Grouped search kernel: G CMI problems that share Y, Z, N and k and differ only in their
+// one-dimensional X column (the candidates and permutation surrogates of one greedy step)
+// are searched together, one 256-query tile per work-group.
+//
+// For every ordered pair (i, j) the Y/Z part of the max-norm distance,
+//   d^YZ_ij = max(|y_j - y_i|, |z_j1 - z_i1|, ..., |z_jm - z_im|),
+// is the same for all G problems, so it is computed once per pair and reused:
+//   joint  d_ij(g)    = max(|x_g,j - x_g,i|, d^YZ_ij)          (pass 1: radius eps_i(g))
+//   counts d^XZ_ij(g) = max(|x_g,j - x_g,i|, d^Z_ij)           (pass 2: n_XZ, n_YZ, n_Z)
+// Every distance, radius and count is bit-identical to the single-problem kernel (the same
+// FP32 subtractions and exact maxima, only evaluated once instead of G times), so the
+// estimates are unchanged.  Column data come from one device pool through 32-bit offsets
+// held in SGPRs; references arrive through the scalar data path as in the single-problem
+// kernel.
+#pragma once
+
+#include "ksg_search.inc.h"
+
+namespace ksg {
+
+typedef float ksg_f4 __attribute__((ext_vector_type(4)));
+typedef const KSG_AS4 ksg_f4* cf4ptr;
+
+// U = 4 references per step: every column is read with one s_load_dwordx4 per step.
+template <int M, int G, int KP>
+__device__ __forceinline__ void group_tile(const float* __restrict__ base,
+                                           const KSG_AS4 GroupDesc* gd, int tile,
+                                           const double* __restrict__ htab,
+                                           double* __restrict__ partials,
+                                           double (*s_red)[G]) {
+  constexpr int U = 4;
+  const int n = gd->n;
+  const int n_pad = gd->n_pad;
+  const int k = gd->k;
+  const int ng = gd->ng;
+  const int qraw = tile * kTileQ + (int)threadIdx.x;
+  const bool valid = qraw < n;
+  const int qi = valid ? qraw : n - 1;
+
+  // Column pointers (wave-uniform, 16-byte aligned: offsets are multiples of the padding).
+  cf4ptr px[G], pz[M > 0 ? M : 1];
+  const float* cy = base + gd->y_off;
+  const cf4ptr py = (cf4ptr)cy;
+  float qx[G], qz[M > 0 ? M : 1];
+  const float qy = cy[qi];
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const float* c = base + gd->x_off[g];
+    px[g] = (cf4ptr)c;
+    qx[g] = c[qi];
+  }
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    const float* c = base + gd->z_off[a];
+    pz[a] = (cf4ptr)c;
+    qz[a] = c[qi];
+  }
+  const int steps = n_pad / U;
+
+  // ---- pass 1: (k+1) smallest joint distances per problem, self included ----
+  // max(|t|, dyz) is taken as med3(|t|, dyz, +inf) and the "any candidate below the radius"
+  // test as an unsigned minimum of the (non-negative) distance bit patterns: neither form
+  // needs the NaN-quieting copies that an IEEE-mode maximum of a value from another basic
+  // block would get, and both give exactly the maximum / comparison of the values.
+  float b[G][KP];
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int i = 0; i < KP; ++i) b[g][i] = (i < KP - 1 - k) ? -INFINITY : INFINITY;
+
+  for (int s = 0; s < steps; ++s) {
+    const ksg_f4 ry = py[s];
+    float dyz[U] = {fabsf(ry.x - qy), fabsf(ry.y - qy), fabsf(ry.z - qy), fabsf(ry.w - qy)};
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      const ksg_f4 rz = pz[a][s];
+      dyz[0] = fmaxf(dyz[0], fabsf(rz.x - qz[a]));
+      dyz[1] = fmaxf(dyz[1], fabsf(rz.y - qz[a]));
+      dyz[2] = fmaxf(dyz[2], fabsf(rz.z - qz[a]));
+      dyz[3] = fmaxf(dyz[3], fabsf(rz.w - qz[a]));
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const ksg_f4 rx = px[g][s];
+      float d[U];
+      d[0] = __builtin_amdgcn_fmed3f(fabsf(rx.x - qx[g]), dyz[0], INFINITY);
+      d[1] = __builtin_amdgcn_fmed3f(fabsf(rx.y - qx[g]), dyz[1], INFINITY);
+      d[2] = __builtin_amdgcn_fmed3f(fabsf(rx.z - qx[g]), dyz[2], INFINITY);
+      d[3] = __builtin_amdgcn_fmed3f(fabsf(rx.w - qx[g]), dyz[3], INFINITY);
+      const unsigned lo = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
+                              min(__float_as_uint(d[2]), __float_as_uint(d[3])));
+      if (lo < __float_as_uint(b[g][KP - 1])) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) topk_insert<KP>(b[g], d[u]);
+      }
+    }
+  }
+  float eps[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) eps[g] = b[g][KP - 1];
+
+  // ---- pass 2: strict counts, self included ----
+  unsigned cxz[G], cyz[G], cz[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) cxz[g] = cyz[g] = cz[g] = 0u;
+  for (int s = 0; s < steps; ++s) {
+    const ksg_f4 ry = py[s];
+    float dz[U], dyz[U];
+    if constexpr (M > 0) {
+      const ksg_f4 r0 = pz[0][s];
+      dz[0] = fabsf(r0.x - qz[0]);
+      dz[1] = fabsf(r0.y - qz[0]);
+      dz[2] = fabsf(r0.z - qz[0]);
+      dz[3] = fabsf(r0.w - qz[0]);
+#pragma unroll
+      for (int a = 1; a < M; ++a) {
+        const ksg_f4 rz = pz[a][s];
+        dz[0] = fmaxf(dz[0], fabsf(rz.x - qz[a]));
+        dz[1] = fmaxf(dz[1], fabsf(rz.y - qz[a]));
+        dz[2] = fmaxf(dz[2], fabsf(rz.z - qz[a]));
+        dz[3] = fmaxf(dz[3], fabsf(rz.w - qz[a]));
+      }
+      dyz[0] = fmaxf(fabsf(ry.x - qy), dz[0]);
+      dyz[1] = fmaxf(fabsf(ry.y - qy), dz[1]);
+      dyz[2] = fmaxf(fabsf(ry.z - qy), dz[2]);
+      dyz[3] = fmaxf(fabsf(ry.w - qy), dz[3]);
+    } else {
+      dz[0] = dz[1] = dz[2] = dz[3] = 0.0f;
+      dyz[0] = fabsf(ry.x - qy);
+      dyz[1] = fabsf(ry.y - qy);
+      dyz[2] = fabsf(ry.z - qy);
+      dyz[3] = fabsf(ry.w - qy);
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const ksg_f4 rx = px[g][s];
+      const float t[U] = {fabsf(rx.x - qx[g]), fabsf(rx.y - qx[g]), fabsf(rx.z - qx[g]),
+                          fabsf(rx.w - qx[g])};
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const float dxz = M > 0 ? fmaxf(t[u], dz[u]) : t[u];
+        cxz[g] += (unsigned)(dxz < eps[g]);
+        cyz[g] += (unsigned)(dyz[u] < eps[g]);
+        if constexpr (M > 0) cz[g] += (unsigned)(dz[u] < eps[g]);
+      }
+    }
+  }
+
+  // ---- epilogue: self correction, digamma terms, one partial per (problem, tile) ----
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int self = eps[g] > 0.0f ? 1 : 0;
+    const int nxz = max((int)cxz[g] - self, 0);
+    const int nyz = max((int)cyz[g] - self, 0);
+    const int nz = M == 0 ? (self ? n - 1 : 0) : max((int)cz[g] - self, 0);
+    double t = valid ? (htab[nxz] + htab[nyz]) - htab[nz] : 0.0;
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) s_red[wave][g] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < ng)
+    partials[gd->part_base + threadIdx.x * gd->n_tiles + tile] =
+        (s_red[0][threadIdx.x] + s_red[1][threadIdx.x]) + (s_red[2][threadIdx.x] + s_red[3][threadIdx.x]);
+}
+
+// One work-group per work item (group, tile); items with group < 0 are XCD padding.
+template <int M, int G, int KP>
+__global__ __launch_bounds__(kTileQ) void ksg_group_kernel(const float* __restrict__ base,
+                                                           const GroupDesc* __restrict__ descs,
+                                                           const WorkItem* __restrict__ items,
+                                                           const double* __restrict__ htab,
+                                                           double* __restrict__ partials) {
+  __shared__ double s_red[kTileQ / 64][G];
+  const KSG_AS4 WorkItem* i4 = (const KSG_AS4 WorkItem*)items;
+  const int grp = i4[blockIdx.x].prob;
+  if (grp < 0) return;
+  const int tile = i4[blockIdx.x].tile;
+  const KSG_AS4 GroupDesc* gd = (const KSG_AS4 GroupDesc*)descs + grp;
+  group_tile<M, G, KP>(base, gd, tile, htab, partials, s_red);
+}
+
+}  // namespace ksg

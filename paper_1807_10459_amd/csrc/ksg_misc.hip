@@ -16,6 +16,10 @@ namespace ksg {
 extern const void* search_kernels_kp5[40];
 extern const void* search_kernels_kp9[40];
 extern const void* search_kernels_kp17[40];
+extern const void* group_kernels_kp5_g8[15];
+extern const void* group_kernels_kp5_g16[15];
+extern const void* group_kernels_kp9_g8[15];
+extern const void* group_kernels_kp9_g16[15];
 
 // ------------------------------------------------------------------ packing
 
@@ -173,6 +177,22 @@ hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, in
   double* a3 = d_partials;
   void* args[] = {&a0, &a1, &a2, &a3};
   return hipLaunchKernel(fn, dim3(n_items), dim3(kTileQ), args, 0, stream);
+}
+
+hipError_t launch_ksg_group(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
+                            int n_items, const double* d_htab, double* d_partials, int m, int G,
+                            int kp, hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  if (m < 0 || m > 14 || (G != 8 && G != 16) || (kp != 5 && kp != 9)) return hipErrorInvalidValue;
+  const void* const* table = kp == 5 ? (G == 8 ? group_kernels_kp5_g8 : group_kernels_kp5_g16)
+                                     : (G == 8 ? group_kernels_kp9_g8 : group_kernels_kp9_g16);
+  const float* a0 = base;
+  const GroupDesc* a1 = d_gdesc;
+  const WorkItem* a2 = d_items;
+  const double* a3 = d_htab;
+  double* a4 = d_partials;
+  void* args[] = {&a0, &a1, &a2, &a3, &a4};
+  return hipLaunchKernel(table[m], dim3(n_items), dim3(kTileQ), args, 0, stream);
 }
 
 hipError_t launch_finalize(const ProbDesc* d_desc, int n_probs, const double* d_partials,

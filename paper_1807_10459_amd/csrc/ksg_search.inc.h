@@ -283,6 +283,7 @@ __global__ __launch_bounds__(kTileQ) void ksg_batch_kernel(const ProbDesc* __res
   const KSG_AS4 WorkItem* i4 = (const KSG_AS4 WorkItem*)items;
   const int it = blockIdx.x;
   const int prob = i4[it].prob;
+  if (prob < 0) return;
   const int tile = i4[it].tile;
   const KSG_AS4 ProbDesc* pd = d4 + prob;
   if constexpr (SHAPE >= 0 && SHAPE < kGenericShape) {

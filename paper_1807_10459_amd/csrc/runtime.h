@@ -45,7 +45,8 @@ struct ksg_ctx {
   std::string err;
 
   bool check_finite = true;
-  int tile_variant = -1;
+  int group_size = -1;           // -1: tuned per conditioning dimension, 0: no grouping, 8 or 16
+  int tuned_g[2][15] = {{0}};    // [k <= 4 ? 0 : 1][m]: group size picked by the autotuner (0 = default)
   bool use_graph = true;
 
   ksg::DevBuf htab, pool, desc, items, partials, jobs, tmp, embed, cmi, aux, feat;
@@ -61,6 +62,12 @@ struct ksg_ctx {
   bool staging_pending = false;
 
   int64_t last_items = 0;
+  int64_t last_groups = 0;
+  int tuned_group_size(int m, int k) const {
+    const int t = tuned_g[k <= 4 ? 0 : 1][m < 15 ? m : 14];
+    return t ? t : 16;
+  }
+  static double algorithmic_ops(const ksg::Problem& p, int ng);
 
   // KSG_OPT_TIMING: events around each search launch, harvested by ksg_take_timing.
   bool timing = false;

@@ -210,3 +210,55 @@ def test_deterministic(lib, ctx):
     a = ctx.cmi(soa(p.x), soa(p.y), soa(p.z), 4)
     b = ctx.cmi(soa(p.x), soa(p.y), soa(p.z), 4)
     assert a == b
+
+
+@pytest.mark.parametrize("m,k", [(0, 4), (1, 4), (3, 8), (8, 4), (14, 2)])
+def test_grouped_equals_ungrouped_and_oracle(lib, ctx, m, k):
+    """Problems sharing Y and Z (the candidates x surrogates of a greedy step) are searched in
+    groups; every group size gives bit-identical estimates, equal to the oracle's."""
+    import torch
+    g = workloads.rng(600 + m)
+    n, n_cand, n_perm = 700, 5, 13  # 5 x 14 = 70 problems: ragged groups of 8 and 16
+    p = workloads.random_problem(700 + m, n, 1, 1, m, k)
+    cands = g.standard_normal((n_cand, n)).astype(np.float32)
+    cands[1] = (cands[1] + p.y[:, 0]).astype(np.float32)  # one dependent candidate
+    perms = workloads.permutations(n, n_perm, seed=800 + m)
+    y, z = soa(p.y), soa(p.z)
+    dc, dp = dev(cands), dev(perms)
+    probs = [lib.Problem(dc[c], y, z, k, perm_x=None if q == 0 else dp[q - 1])
+             for c in range(n_cand) for q in range(n_perm + 1)]
+    res = {}
+    for gs in (0, 8, 16):
+        ctx.set_option(ctx.OPT_GROUP_SIZE, gs)
+        res[gs] = ctx.cmi_batch(probs).cpu().numpy()
+    ctx.set_option(ctx.OPT_GROUP_SIZE, -1)
+    assert np.array_equal(res[0], res[8]) and np.array_equal(res[0], res[16])
+    for idx in (0, 1, 15, 16, 17, 69):
+        c, q = divmod(idx, n_perm + 1)
+        x = cands[c] if q == 0 else cands[c][perms[q - 1]]
+        ref = ksg_cmi(x, p.y, p.z, k)
+        assert abs(res[8][idx] - ref) <= tol(ref), idx
+
+
+def test_many_groups_xcd_order(lib, ctx):
+    """Enough groups for the XCD-interleaved work order (with empty slots); still exact."""
+    g = workloads.rng(900)
+    n, n_cand, n_perm = 300, 40, 15  # 640 problems -> 40 groups of 16 / 80 groups of 8
+    p = workloads.random_problem(901, n, 1, 1, 2, 4)
+    cands = g.standard_normal((n_cand, n)).astype(np.float32)
+    perms = workloads.permutations(n, n_perm, seed=902)
+    y, z = soa(p.y), soa(p.z)
+    dc, dp = dev(cands), dev(perms)
+    probs = [lib.Problem(dc[c], y, z, 4, perm_x=None if q == 0 else dp[q - 1])
+             for c in range(n_cand) for q in range(n_perm + 1)]
+    ctx.set_option(ctx.OPT_GROUP_SIZE, 0)
+    ref_all = ctx.cmi_batch(probs).cpu().numpy()
+    for gs in (8, 16):
+        ctx.set_option(ctx.OPT_GROUP_SIZE, gs)
+        assert np.array_equal(ctx.cmi_batch(probs).cpu().numpy(), ref_all)
+    ctx.set_option(ctx.OPT_GROUP_SIZE, -1)
+    for idx in (0, 333, 639):
+        c, q = divmod(idx, n_perm + 1)
+        x = cands[c] if q == 0 else cands[c][perms[q - 1]]
+        ref = ksg_cmi(x, p.y, p.z, 4)
+        assert abs(ref_all[idx] - ref) <= tol(ref)
