@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--group-size", type=int, default=-1,
+                    help="problems searched together (-1 tuned, 0 off, 8, 16)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (a known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -106,6 +108,7 @@ def main():
     data = torch.from_numpy(net.data).cuda()
     perms = torch.from_numpy(perms_np).cuda()
     ctx = ksg.Context(0)
+    ctx.set_option(ctx.OPT_GROUP_SIZE, args.group_size)
     tables = {m: torch.empty((25 - m, N_PERM + 1), dtype=torch.float64, device="cuda") for m in FORCED_M}
 
     def step():
@@ -143,7 +146,9 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_VALU, 4),
         "traffic": None,
-        "kernel": "ksg_batch_kernel (k-NN radius + strict counts + digamma partial sums)",
+        "kernel": "ksg_group_kernel (k-NN radius + strict counts + digamma partial sums, "
+                  "Y/Z distances shared by each group of candidates/surrogates)" if args.group_size != 0
+                  else "ksg_batch_kernel (k-NN radius + strict counts + digamma partial sums)",
         "kernel_ms_per_launch": round(k_ms / max(k_launches, 1), 3),
         "launches": k_launches,
         "ops_per_launch": k_ops / max(k_launches, 1),
