@@ -30,17 +30,25 @@ struct alignas(16) ProbDesc {
 };
 
 // G problems that share Y (1-D), Z (m columns), N and k and differ in a 1-D X column.
-// Column data live in one pool; offsets are in floats.  Problem g of the group writes its
-// per-tile partial sums at part_base + g * n_tiles + tile.
+// All offsets are in floats from one pool.  x_off / y_off / z_off locate the packed source
+// columns; xi_off / yzi_off the interleaved blocks the search kernel reads:
+//   X block  [n_pad/4][G][4]   (G = the kernel's group size; unused slots repeat column 0)
+//   YZ block [n_pad/4][m+1][4] (Y first), shared by every group with the same Y and Z and
+//   written by the group with write_yz = 1.
+// Problem g of the group writes its per-tile partial sums at part_base + g * n_tiles + tile.
 constexpr int kGroupMax = 16;
 struct alignas(16) GroupDesc {
   uint32_t x_off[kGroupMax];
   uint32_t y_off;
   uint32_t z_off[kMaxDims - 2];
+  uint32_t xi_off;
+  uint32_t yzi_off;
   int32_t n, n_pad, k, m;
-  int32_t ng;         // problems in this group (the rest of x_off repeats a valid column)
+  int32_t ng;         // problems in this group
+  int32_t G;          // group size of the kernel that searches it
   int32_t n_tiles;
   int32_t part_base;
+  int32_t write_yz;
   int32_t pad_[2];
 };
 
@@ -96,6 +104,8 @@ hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, in
 hipError_t launch_ksg_group(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
                             int n_items, const double* d_htab, double* d_partials, int m, int G,
                             int kp, hipStream_t stream);
+hipError_t launch_interleave(const GroupDesc* d_gdesc, int n_groups, int max_pad, float* base,
+                             hipStream_t stream);
 hipError_t launch_finalize(const ProbDesc* d_desc, int n_probs, const double* d_partials,
                            const double* d_htab, double* d_out, hipStream_t stream);
 

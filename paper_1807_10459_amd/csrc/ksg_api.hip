@@ -384,6 +384,27 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       col_off[i][a] = it->second;
     }
   }
+  // Interleaved blocks of the groups follow the packed columns in the same pool.
+  std::vector<int64_t> xi_off(groups.size()), yzi_off(groups.size());
+  std::vector<int> write_yz(groups.size(), 0);
+  {
+    std::map<std::vector<int64_t>, int64_t> yz_sets;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const int i0 = groups[gi][0];
+      const int64_t n_pad = round_up(probs[i0].n, kPad);
+      xi_off[gi] = pool_floats;
+      pool_floats += (int64_t)group_size_of[gi] * n_pad;
+      std::vector<int64_t> key = {n_pad};
+      for (int a = 1; a < 2 + probs[i0].dz; ++a) key.push_back(col_off[i0][a]);
+      auto it = yz_sets.find(key);
+      if (it == yz_sets.end()) {
+        it = yz_sets.emplace(key, pool_floats).first;
+        pool_floats += (int64_t)(probs[i0].dz + 1) * n_pad;
+        write_yz[gi] = 1;
+      }
+      yzi_off[gi] = it->second;
+    }
+  }
   if (!groups.empty() && pool_floats > (int64_t)UINT32_MAX)
     return fail(KSG_ENOMEM, "batch needs %lld pool floats, above the 2^32 addressable by groups",
                 (long long)pool_floats);
@@ -477,6 +498,10 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     }
     gd.y_off = (uint32_t)col_off[i0][1];
     for (int a = 0; a < p0.dz; ++a) gd.z_off[a] = (uint32_t)col_off[i0][2 + a];
+    gd.xi_off = (uint32_t)xi_off[gi];
+    gd.yzi_off = (uint32_t)yzi_off[gi];
+    gd.write_yz = write_yz[gi];
+    gd.G = group_size_of[gi];
     gd.n = (int)p0.n;
     gd.n_pad = (int)round_up(p0.n, kPad);
     gd.k = p0.k;
@@ -546,6 +571,9 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     st = check_columns_finite(all, max_pad);
     if (st) return st;
   }
+  const GroupDesc* d_gdesc = (const GroupDesc*)((char*)desc.ptr + sz_desc);
+  if (!groups.empty())
+    KSG_HIP(this, launch_interleave(d_gdesc, (int)groups.size(), max_pad, pool_base, stream));
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (timing) {
     t0 = get_event();
@@ -554,7 +582,6 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     KSG_HIP(this, hipEventRecord(t0, stream));
   }
   const WorkItem* d_items = (const WorkItem*)this->items.ptr;
-  const GroupDesc* d_gdesc = (const GroupDesc*)((char*)desc.ptr + sz_desc);
   {
     size_t ci = 0;
     for (auto& kv : classes) {

@@ -21,7 +21,11 @@ namespace ksg {
 typedef float ksg_f4 __attribute__((ext_vector_type(4)));
 typedef const KSG_AS4 ksg_f4* cf4ptr;
 
-// U = 4 references per step: every column is read with one s_load_dwordx4 per step.
+// Interleaved group blocks (written by the interleave kernel from the packed columns):
+//   X block  [n_pad/4][G][4]:   the G candidate columns, four references at a time,
+//   YZ block [n_pad/4][M+1][4]: Y then the M conditioning columns, four references at a time.
+// One step of U = 4 references reads G + M + 1 consecutive float4 values from two pointers,
+// so the scalar loads of a step share two base registers and are issued together.
 template <int M, int G, int KP>
 __device__ __forceinline__ void group_tile(const float* __restrict__ base,
                                            const KSG_AS4 GroupDesc* gd, int tile,
@@ -29,6 +33,7 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
                                            double* __restrict__ partials,
                                            double (*s_red)[G]) {
   constexpr int U = 4;
+  constexpr int W = M + 1;
   const int n = gd->n;
   const int n_pad = gd->n_pad;
   const int k = gd->k;
@@ -37,24 +42,17 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
   const bool valid = qraw < n;
   const int qi = valid ? qraw : n - 1;
 
-  // Column pointers (wave-uniform, 16-byte aligned: offsets are multiples of the padding).
-  cf4ptr px[G], pz[M > 0 ? M : 1];
-  const float* cy = base + gd->y_off;
-  const cf4ptr py = (cf4ptr)cy;
+  const float* xi = base + gd->xi_off;
+  const float* yzi = base + gd->yzi_off;
+  const cf4ptr px = (cf4ptr)xi;
+  const cf4ptr pyz = (cf4ptr)yzi;
   float qx[G], qz[M > 0 ? M : 1];
-  const float qy = cy[qi];
+  const int qs = qi >> 2, ql = qi & 3;
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const float* c = base + gd->x_off[g];
-    px[g] = (cf4ptr)c;
-    qx[g] = c[qi];
-  }
+  for (int g = 0; g < G; ++g) qx[g] = xi[(qs * G + g) * 4 + ql];
+  const float qy = yzi[(qs * W) * 4 + ql];
 #pragma unroll
-  for (int a = 0; a < M; ++a) {
-    const float* c = base + gd->z_off[a];
-    pz[a] = (cf4ptr)c;
-    qz[a] = c[qi];
-  }
+  for (int a = 0; a < M; ++a) qz[a] = yzi[(qs * W + 1 + a) * 4 + ql];
   const int steps = n_pad / U;
 
   // ---- pass 1: (k+1) smallest joint distances per problem, self included ----
@@ -69,11 +67,14 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
     for (int i = 0; i < KP; ++i) b[g][i] = (i < KP - 1 - k) ? -INFINITY : INFINITY;
 
   for (int s = 0; s < steps; ++s) {
-    const ksg_f4 ry = py[s];
+    ksg_f4 rx[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) rx[g] = px[s * G + g];
+    const ksg_f4 ry = pyz[s * W];
     float dyz[U] = {fabsf(ry.x - qy), fabsf(ry.y - qy), fabsf(ry.z - qy), fabsf(ry.w - qy)};
 #pragma unroll
     for (int a = 0; a < M; ++a) {
-      const ksg_f4 rz = pz[a][s];
+      const ksg_f4 rz = pyz[s * W + 1 + a];
       dyz[0] = fmaxf(dyz[0], fabsf(rz.x - qz[a]));
       dyz[1] = fmaxf(dyz[1], fabsf(rz.y - qz[a]));
       dyz[2] = fmaxf(dyz[2], fabsf(rz.z - qz[a]));
@@ -81,12 +82,11 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const ksg_f4 rx = px[g][s];
       float d[U];
-      d[0] = __builtin_amdgcn_fmed3f(fabsf(rx.x - qx[g]), dyz[0], INFINITY);
-      d[1] = __builtin_amdgcn_fmed3f(fabsf(rx.y - qx[g]), dyz[1], INFINITY);
-      d[2] = __builtin_amdgcn_fmed3f(fabsf(rx.z - qx[g]), dyz[2], INFINITY);
-      d[3] = __builtin_amdgcn_fmed3f(fabsf(rx.w - qx[g]), dyz[3], INFINITY);
+      d[0] = __builtin_amdgcn_fmed3f(fabsf(rx[g].x - qx[g]), dyz[0], INFINITY);
+      d[1] = __builtin_amdgcn_fmed3f(fabsf(rx[g].y - qx[g]), dyz[1], INFINITY);
+      d[2] = __builtin_amdgcn_fmed3f(fabsf(rx[g].z - qx[g]), dyz[2], INFINITY);
+      d[3] = __builtin_amdgcn_fmed3f(fabsf(rx[g].w - qx[g]), dyz[3], INFINITY);
       const unsigned lo = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
                               min(__float_as_uint(d[2]), __float_as_uint(d[3])));
       if (lo < __float_as_uint(b[g][KP - 1])) {
@@ -104,17 +104,17 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
 #pragma unroll
   for (int g = 0; g < G; ++g) cxz[g] = cyz[g] = cz[g] = 0u;
   for (int s = 0; s < steps; ++s) {
-    const ksg_f4 ry = py[s];
+    const ksg_f4 ry = pyz[s * W];
     float dz[U], dyz[U];
     if constexpr (M > 0) {
-      const ksg_f4 r0 = pz[0][s];
+      const ksg_f4 r0 = pyz[s * W + 1];
       dz[0] = fabsf(r0.x - qz[0]);
       dz[1] = fabsf(r0.y - qz[0]);
       dz[2] = fabsf(r0.z - qz[0]);
       dz[3] = fabsf(r0.w - qz[0]);
 #pragma unroll
       for (int a = 1; a < M; ++a) {
-        const ksg_f4 rz = pz[a][s];
+        const ksg_f4 rz = pyz[s * W + 1 + a];
         dz[0] = fmaxf(dz[0], fabsf(rz.x - qz[a]));
         dz[1] = fmaxf(dz[1], fabsf(rz.y - qz[a]));
         dz[2] = fmaxf(dz[2], fabsf(rz.z - qz[a]));
@@ -133,7 +133,7 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
     }
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      const ksg_f4 rx = px[g][s];
+      const ksg_f4 rx = px[s * G + g];
       const float t[U] = {fabsf(rx.x - qx[g]), fabsf(rx.y - qx[g]), fabsf(rx.z - qx[g]),
                           fabsf(rx.w - qx[g])};
 #pragma unroll

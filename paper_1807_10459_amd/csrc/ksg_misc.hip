@@ -104,6 +104,42 @@ hipError_t launch_perm_check(const int32_t* perms, int n_perm, int n, int* d_fla
   return hipGetLastError();
 }
 
+// Interleaved group blocks from packed columns (layouts in internal.h).  grid.x: chunks of
+// 64 four-row steps, grid.y: groups (strided).
+__global__ __launch_bounds__(256) void interleave_kernel(const GroupDesc* __restrict__ descs,
+                                                         int n_groups, float* __restrict__ base) {
+  for (int gi = blockIdx.y; gi < n_groups; gi += gridDim.y) {
+    const GroupDesc& gd = descs[gi];
+    const int steps = gd.n_pad / 4;
+    const int s0 = blockIdx.x * 64;
+    if (s0 >= steps) continue;
+    const int s1 = min(steps, s0 + 64);
+    const int G = gd.G;
+    float* xi = base + gd.xi_off;
+    for (int e = s0 * G * 4 + threadIdx.x; e < s1 * G * 4; e += 256) {
+      const int s = e / (G * 4), r = e - s * G * 4, g = r >> 2, u = r & 3;
+      xi[e] = base[gd.x_off[g] + s * 4 + u];
+    }
+    if (gd.write_yz) {
+      const int W = gd.m + 1;
+      float* yzi = base + gd.yzi_off;
+      for (int e = s0 * W * 4 + threadIdx.x; e < s1 * W * 4; e += 256) {
+        const int s = e / (W * 4), r = e - s * W * 4, a = r >> 2, u = r & 3;
+        const uint32_t src = a == 0 ? gd.y_off : gd.z_off[a - 1];
+        yzi[e] = base[src + s * 4 + u];
+      }
+    }
+  }
+}
+
+hipError_t launch_interleave(const GroupDesc* d_gdesc, int n_groups, int max_pad, float* base,
+                             hipStream_t stream) {
+  if (n_groups <= 0) return hipSuccess;
+  dim3 grid((max_pad / 4 + 63) / 64, n_groups < 65535 ? n_groups : 65535);
+  hipLaunchKernelGGL(interleave_kernel, grid, dim3(256), 0, stream, d_gdesc, n_groups, base);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ embedding
 
 // Candidate (v, l) row i: trial tr = i / (T - L), time t = L + i % (T - L), value x_v(t - l).
