@@ -306,6 +306,36 @@ int ksg_step_features(ksg_ctx* ctx, const double* orig_cmi, int32_t c, const flo
                       const float* cand, int64_t N, const int32_t* cand_idx, int32_t dx,
                       int32_t dy, int32_t dz, int32_t k, int32_t n_perm, float* out);
 
+/* Training examples for the threshold network from one greedy step's surrogate table:
+ * every candidate subset of the step (rows of `table`) has its own max-statistic null
+ * distribution (the same round permutations act on every candidate), so each subset gives
+ * one example.  table: device FP64 [rows][n_perm+1] (column 0 = originals; the layout of
+ * ksg_greedy_step); row_cand: host int32 [rows], candidate column of each row; subsets in
+ * CSR form: sub_off host int32 [n_sub+1] (sub_off[0] = 0, strictly increasing), sub_rows
+ * host int32 [sub_off[n_sub]].  cand: device FP32 [C][N]; y: device FP32 [N]; dz: the
+ * step's conditioning dimension.  Outputs (device): feats FP32 [n_sub][16] (the step
+ * features of the subset), targets FP32 [n_sub][2] = sqrt(N) * (tau_0.05, tau_0.01), obs
+ * FP64 [n_sub][2] = (sqrt(N) * t_obs, 1.0 if the plain test is significant at 0.05 else 0.0).
+ * Synchronises.  Errors: KSG_EINVAL, KSG_ENOMEM, KSG_EDEVICE. */
+int ksg_null_examples(ksg_ctx* ctx, const double* table, int32_t rows, int32_t n_perm,
+                      const int32_t* row_cand, const int32_t* sub_off, const int32_t* sub_rows,
+                      int32_t n_sub, const float* cand, int32_t C, const float* y, int64_t N,
+                      int32_t dz, int32_t k, float* feats, float* targets, double* obs);
+
+/* Set the network's feature standardisation to the per-feature mean and population
+ * standard deviation of feats (device FP32 [B][16]).  Synchronises. */
+int ksg_mlp_fit_norm(ksg_ctx* ctx, ksg_mlp* m, const float* feats, int64_t B);
+
+/* Calibrate the gate margins on held-out examples (feats [B][16] and obs [B][2] as written by
+ * ksg_null_examples, device): with u = (sqrt(N) t_obs - pred_0.05) / |pred_0.01 - pred_0.05|,
+ * the gate includes when u > margin_hi and stops when u < -margin_lo; each margin is the
+ * smallest value >= 0 that leaves at most floor(rate/2 * B) examples decided against the
+ * plain test on its side.  Outputs (host): margins, the fraction of examples left to the
+ * surrogate test (fallback) and the number decided wrongly (wrong).  Synchronises. */
+int ksg_gate_calibrate(ksg_ctx* ctx, const ksg_mlp* m, const float* feats, const double* obs,
+                       int64_t B, double rate, double* margin_lo, double* margin_hi,
+                       double* fallback, int64_t* wrong);
+
 #ifdef __cplusplus
 }
 #endif

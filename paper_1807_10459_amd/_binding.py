@@ -87,6 +87,10 @@ def _load():
         "ksg_mlp_train": ([vp, vp, vp, vp, i64, i32, i32, f, vp], i32),
         "ksg_mlp_save": ([vp, C.c_char_p], i32),
         "ksg_mlp_load": ([vp, C.POINTER(vp), C.c_char_p], i32),
+        "ksg_null_examples": ([vp, vp, i32, i32, vp, vp, vp, i32, vp, i32, vp, i64, i32, i32, vp, vp, vp], i32),
+        "ksg_mlp_fit_norm": ([vp, vp, vp, i64], i32),
+        "ksg_gate_calibrate": ([vp, vp, vp, vp, i64, d, C.POINTER(d), C.POINTER(d), C.POINTER(d),
+                                C.POINTER(i64)], i32),
         "ksg_step_features": ([vp, vp, i32, vp, vp, i64, vp, i32, i32, i32, i32, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -292,6 +296,23 @@ class Context:
                     omnibus_significant=bool(ps.omnibus_significant), omnibus_cmi=ps.omnibus_cmi,
                     omnibus_pval=ps.omnibus_pval, n_cmi=ps.n_cmi)
 
+    def null_examples(self, table, row_cand, subsets, cand, y, dz: int, k: int = 4):
+        """Training examples from one step's surrogate table (see ksg_null_examples)."""
+        import torch
+        _check_dtype(table, torch.float64, "table")
+        rows, p1 = table.shape
+        rc = np.ascontiguousarray(np.asarray(row_cand, np.int32))
+        off, sr = _csr(subsets)
+        n_sub = len(subsets)
+        feats = torch.empty((n_sub, MLP_NFEAT), dtype=torch.float32, device=table.device)
+        targ = torch.empty((n_sub, 2), dtype=torch.float32, device=table.device)
+        obs = torch.empty((n_sub, 2), dtype=torch.float64, device=table.device)
+        self._check(lib.ksg_null_examples(self._h, _ptr(table), rows, p1 - 1, rc.ctypes.data, off.ctypes.data,
+                                          sr.ctypes.data, n_sub, _ptr(cand), cand.shape[0], _ptr(y), y.shape[0],
+                                          int(dz), int(k), _ptr(feats), _ptr(targ), _ptr(obs)),
+                    "ksg_null_examples")
+        return feats, targ, obs
+
     def step_features(self, orig_cmi, y, cand, cand_idx, dx, dy, dz, k, n_perm):
         import torch
         _check_dtype(orig_cmi, torch.float64, "orig_cmi")
@@ -301,6 +322,13 @@ class Context:
                                           y.shape[0], idx.ctypes.data, dx, dy, dz, k, n_perm, _ptr(out)),
                     "ksg_step_features")
         return out
+
+
+def _csr(subsets):
+    off = np.zeros(len(subsets) + 1, np.int32)
+    off[1:] = np.cumsum([len(s) for s in subsets])
+    rows = np.ascontiguousarray(np.concatenate([np.asarray(s, np.int32) for s in subsets]))
+    return off, rows
 
 
 class ThresholdNet:
@@ -359,6 +387,16 @@ class ThresholdNet:
         st = lib.ksg_mlp_set_params(self._h, p.ctypes.data)
         if st:
             raise KsgError(st, "ksg_mlp_set_params")
+
+    def fit_norm(self, feats):
+        self.ctx._check(lib.ksg_mlp_fit_norm(self.ctx._h, self._h, _ptr(feats), feats.shape[0]), "ksg_mlp_fit_norm")
+
+    def calibrate(self, feats, obs, rate: float = 0.0025) -> dict:
+        lo, hi, fb, wrong = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+        self.ctx._check(lib.ksg_gate_calibrate(self.ctx._h, self._h, _ptr(feats), _ptr(obs), feats.shape[0],
+                                               float(rate), C.byref(lo), C.byref(hi), C.byref(fb), C.byref(wrong)),
+                        "ksg_gate_calibrate")
+        return dict(margin_lo=lo.value, margin_hi=hi.value, fallback=fb.value, wrong=wrong.value)
 
     def forward(self, feats):
         import torch

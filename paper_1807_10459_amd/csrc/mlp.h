@@ -54,6 +54,12 @@ hipError_t launch_step_features(const double* cmi, int stride, int c, const int3
                                 const double* y_mom, const double* cand_mom, int n, int dx, int dy,
                                 int dz, int k, int n_perm, float* feat, double* obs,
                                 hipStream_t stream);
+hipError_t launch_null_examples(const double* table, int P, const int32_t* sub_off,
+                                const int32_t* sub_rows, int n_sub, const int32_t* row_cand,
+                                const double* cand_mom, const double* y_mom, int n, int dx, int dy,
+                                int dz, int k, float* feats, float* targ, double* obs,
+                                hipStream_t stream);
+hipError_t launch_feature_norm(const float* feats, int64_t B, float* mu, float* sd, hipStream_t stream);
 hipError_t launch_gate(const float* pred, const double* obs, int n, double margin_lo,
                        double margin_hi, int* verdict, hipStream_t stream);
 

@@ -3,7 +3,9 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "../../include/ksgcmi.h"
@@ -320,3 +322,105 @@ int LearnedGate::decide(ksg_ctx* c, const double* d_cmi, int cands, int stride,
 }
 
 }  // namespace ksg
+
+// ============================================================== training data and calibration
+
+extern "C" int ksg_null_examples(ksg_ctx* c, const double* table, int32_t rows, int32_t n_perm,
+                                 const int32_t* row_cand, const int32_t* sub_off,
+                                 const int32_t* sub_rows, int32_t n_sub, const float* cand, int32_t C,
+                                 const float* y, int64_t N, int32_t dz, int32_t k, float* feats,
+                                 float* targets, double* obs) {
+  if (!c) return KSG_EINVAL;
+  if (!table || !row_cand || !sub_off || !sub_rows || !cand || !y || !feats || !targets || !obs)
+    return c->fail(KSG_EINVAL, "ksg_null_examples: null argument");
+  if (rows < 1 || n_perm < 1 || n_perm > 4096 || n_sub < 1 || C < 1 || N < 2 || N > INT32_MAX || dz < 0 || k < 1)
+    return c->fail(KSG_EINVAL, "ksg_null_examples: bad sizes");
+  if (sub_off[0] != 0) return c->fail(KSG_EINVAL, "ksg_null_examples: sub_off[0] must be 0");
+  for (int s = 0; s < n_sub; ++s)
+    if (sub_off[s + 1] <= sub_off[s]) return c->fail(KSG_EINVAL, "ksg_null_examples: empty subset %d", s);
+  const int nidx = sub_off[n_sub];
+  for (int q = 0; q < nidx; ++q)
+    if (sub_rows[q] < 0 || sub_rows[q] >= rows) return c->fail(KSG_EINVAL, "ksg_null_examples: row index out of range");
+  for (int r = 0; r < rows; ++r)
+    if (row_cand[r] < 0 || row_cand[r] >= C) return c->fail(KSG_EINVAL, "ksg_null_examples: candidate index out of range");
+  KSG_HIP(c, hipSetDevice(c->device));
+  const size_t b_mom = sizeof(double) * (size_t)(C + 1) * 3;
+  const size_t b_idx = sizeof(int32_t) * ((size_t)n_sub + 1 + nidx + rows);
+  int st = c->reserve(c->feat, b_mom + b_idx + 64, "example workspace");
+  if (st) return st;
+  double* mom = (double*)c->feat.ptr;
+  int32_t* d_off = (int32_t*)((char*)c->feat.ptr + b_mom);
+  int32_t* d_rows = d_off + n_sub + 1;
+  int32_t* d_rc = d_rows + nidx;
+  std::vector<int32_t> h(n_sub + 1 + nidx + rows);
+  std::memcpy(h.data(), sub_off, sizeof(int32_t) * (n_sub + 1));
+  std::memcpy(h.data() + n_sub + 1, sub_rows, sizeof(int32_t) * nidx);
+  std::memcpy(h.data() + n_sub + 1 + nidx, row_cand, sizeof(int32_t) * rows);
+  KSG_HIP(c, hipMemcpyAsync(d_off, h.data(), b_idx, hipMemcpyHostToDevice, c->stream));
+  KSG_HIP(c, launch_column_moments(cand, N, C, (int)N, mom, c->stream));
+  KSG_HIP(c, launch_column_moments(y, N, 1, (int)N, mom + (size_t)C * 3, c->stream));
+  KSG_HIP(c, launch_null_examples(table, n_perm, d_off, d_rows, n_sub, d_rc, mom, mom + (size_t)C * 3,
+                                  (int)N, 1, 1, dz, k, feats, targets, obs, c->stream));
+  KSG_HIP(c, hipStreamSynchronize(c->stream));
+  return KSG_OK;
+}
+
+extern "C" int ksg_mlp_fit_norm(ksg_ctx* c, ksg_mlp* m, const float* feats, int64_t B) {
+  if (!c) return KSG_EINVAL;
+  if (!m || !feats || B < 1) return c->fail(KSG_EINVAL, "ksg_mlp_fit_norm: bad argument");
+  KSG_HIP(c, hipSetDevice(c->device));
+  KSG_HIP(c, launch_feature_norm(feats, B, m->mu, m->sd, c->stream));
+  KSG_HIP(c, hipMemcpyAsync(m->h_mu, m->mu, sizeof(float) * kNIn, hipMemcpyDeviceToHost, c->stream));
+  KSG_HIP(c, hipMemcpyAsync(m->h_sd, m->sd, sizeof(float) * kNIn, hipMemcpyDeviceToHost, c->stream));
+  KSG_HIP(c, hipStreamSynchronize(c->stream));
+  return KSG_OK;
+}
+
+// Margins of the gate in units of s = |pred_0.01 - pred_0.05|: with u = (sqrt(N) t_obs -
+// pred_0.05) / s, the gate includes when u > margin_hi and stops when u < -margin_lo.  Each
+// margin is the smallest value >= 0 for which at most floor(rate/2 * B) examples are decided
+// against their plain-test outcome on that side.
+extern "C" int ksg_gate_calibrate(ksg_ctx* c, const ksg_mlp* m, const float* feats, const double* obs,
+                                  int64_t B, double rate, double* margin_lo, double* margin_hi,
+                                  double* fallback, int64_t* wrong) {
+  if (!c) return KSG_EINVAL;
+  if (!m || !feats || !obs || B < 1 || !(rate >= 0 && rate < 1) || !margin_lo || !margin_hi || !fallback || !wrong)
+    return c->fail(KSG_EINVAL, "ksg_gate_calibrate: bad argument");
+  KSG_HIP(c, hipSetDevice(c->device));
+  int st = c->reserve(c->tmp, sizeof(float) * 2 * (size_t)B, "predictions");
+  if (st) return st;
+  KSG_HIP(c, launch_mlp_forward(m->wbf16, m->mu, m->sd, feats, B, (float*)c->tmp.ptr, c->stream));
+  std::vector<float> pred(2 * (size_t)B);
+  std::vector<double> ob(2 * (size_t)B);
+  KSG_HIP(c, hipMemcpyAsync(pred.data(), c->tmp.ptr, sizeof(float) * 2 * B, hipMemcpyDeviceToHost, c->stream));
+  KSG_HIP(c, hipMemcpyAsync(ob.data(), obs, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, c->stream));
+  KSG_HIP(c, hipStreamSynchronize(c->stream));
+  std::vector<double> u_neg, u_pos;  // u of plainly non-significant / significant examples
+  std::vector<double> u(B);
+  for (int64_t i = 0; i < B; ++i) {
+    const double s = std::max(std::fabs((double)pred[2 * i + 1] - (double)pred[2 * i]), 1e-30);
+    u[i] = (ob[2 * i] - (double)pred[2 * i]) / s;
+    (ob[2 * i + 1] > 0.5 ? u_pos : u_neg).push_back(u[i]);
+  }
+  const int64_t allow = (int64_t)std::floor(rate / 2.0 * (double)B);
+  // margin_hi: at most `allow` non-significant examples with u > margin_hi
+  std::sort(u_neg.begin(), u_neg.end(), std::greater<double>());
+  double hi = 0.0;
+  if ((int64_t)u_neg.size() > allow) hi = std::max(0.0, u_neg[allow]);
+  // margin_lo: at most `allow` significant examples with u < -margin_lo
+  std::sort(u_pos.begin(), u_pos.end());
+  double lo = 0.0;
+  if ((int64_t)u_pos.size() > allow) lo = std::max(0.0, -u_pos[allow]);
+  int64_t band = 0, bad = 0;
+  for (int64_t i = 0; i < B; ++i) {
+    const bool sig = ob[2 * i + 1] > 0.5;
+    if (u[i] > hi) bad += !sig;
+    else if (u[i] < -lo) bad += sig;
+    else ++band;
+  }
+  *margin_lo = lo;
+  *margin_hi = hi;
+  *fallback = (double)band / (double)B;
+  *wrong = bad;
+  return KSG_OK;
+}

@@ -330,17 +330,130 @@ hipError_t launch_step_features(const double* cmi, int stride, int c, const int3
   return hipGetLastError();
 }
 
+// One block per candidate subset of a step's surrogate table: the subset's max-statistic
+// distribution gives one training example of the threshold network.  table: FP64 [rows][P+1]
+// (column 0 = originals); the subset lists table rows; row_cand maps a row to its candidate
+// column (for the moments).  Outputs: feats [n_sub][16] (the step features of the subset),
+// targ [n_sub][2] = sqrt(N) * (tau_0.05, tau_0.01) (ceil(alpha P)-th largest per-round maximum),
+// obs [n_sub][2] = (sqrt(N) * t_obs, 1 if the plain test is significant at 0.05 else 0).
+constexpr int kMaxPermEx = 4096;
+
+__global__ __launch_bounds__(256) void null_examples_kernel(
+    const double* __restrict__ table, int P, const int32_t* __restrict__ sub_off,
+    const int32_t* __restrict__ sub_rows, const int32_t* __restrict__ row_cand,
+    const double* __restrict__ cand_mom, const double* __restrict__ y_mom, int n, int dx, int dy,
+    int dz, int k, float* __restrict__ feats, float* __restrict__ targ, double* __restrict__ obs) {
+  __shared__ double tmax[kMaxPermEx];
+  __shared__ int s_count;
+  const int sb = blockIdx.x;
+  const int r0 = sub_off[sb], r1 = sub_off[sb + 1];
+  const int c = r1 - r0;
+  if (threadIdx.x == 0) s_count = 0;
+  __syncthreads();
+  // observed statistic and its candidate (lowest row position wins ties)
+  double t_obs = table[(int64_t)sub_rows[r0] * (P + 1)];
+  for (int q = r0 + 1; q < r1; ++q) t_obs = fmax(t_obs, table[(int64_t)sub_rows[q] * (P + 1)]);
+  int local = 0;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    double m = table[(int64_t)sub_rows[r0] * (P + 1) + p + 1];
+    for (int q = r0 + 1; q < r1; ++q) m = fmax(m, table[(int64_t)sub_rows[q] * (P + 1) + p + 1]);
+    tmax[p] = m;
+    local += m >= t_obs ? 1 : 0;
+  }
+  atomicAdd(&s_count, local);
+  __syncthreads();
+  const int rk05 = min(max((int)ceil(0.05 * P), 1), P);
+  const int rk01 = min(max((int)ceil(0.01 * P), 1), P);
+  const double rn = sqrt((double)n);
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const double v = tmax[p];
+    int rank = 0;
+    for (int q = 0; q < P; ++q) rank += (tmax[q] > v) || (tmax[q] == v && q < p);
+    if (rank == rk05 - 1) targ[sb * 2 + 0] = (float)(rn * v);
+    if (rank == rk01 - 1) targ[sb * 2 + 1] = (float)(rn * v);
+  }
+  if (threadIdx.x == 0) {
+    double first = -INFINITY, second = -INFINITY, sum = 0.0;
+    int best = -1;
+    for (int q = r0; q < r1; ++q) {
+      const double v = table[(int64_t)sub_rows[q] * (P + 1)];
+      sum += v;
+      if (best < 0 || v > first) {
+        best = q;
+        first = v;
+      }
+    }
+    for (int q = r0; q < r1; ++q)
+      if (q != best) second = fmax(second, table[(int64_t)sub_rows[q] * (P + 1)]);
+    if (c == 1) second = first;
+    const double mean = sum / c;
+    double var = 0.0, sk = 0.0, ku = 0.0, ac = 0.0;
+    for (int q = r0; q < r1; ++q) {
+      const double d = table[(int64_t)sub_rows[q] * (P + 1)] - mean;
+      var += d * d;
+      const double* cm = cand_mom + (int64_t)row_cand[sub_rows[q]] * 3;
+      sk += cm[0];
+      ku += cm[1];
+      ac += fabs(cm[2]);
+    }
+    const double f[kNIn] = {log((double)n), (double)dx, (double)dy, (double)dz, (double)k,
+                            log((double)c), log((double)P), rn * first, rn * second, rn * mean,
+                            rn * sqrt(var / c), y_mom[0], y_mom[1], sk / c, ku / c, ac / c};
+    for (int i = 0; i < kNIn; ++i) feats[sb * kNIn + i] = (float)f[i];
+    obs[sb * 2 + 0] = rn * t_obs;
+    obs[sb * 2 + 1] = ((double)s_count / (double)P) < 0.05 ? 1.0 : 0.0;
+  }
+}
+
+hipError_t launch_null_examples(const double* table, int P, const int32_t* sub_off,
+                                const int32_t* sub_rows, int n_sub, const int32_t* row_cand,
+                                const double* cand_mom, const double* y_mom, int n, int dx, int dy,
+                                int dz, int k, float* feats, float* targ, double* obs,
+                                hipStream_t stream) {
+  if (n_sub <= 0) return hipSuccess;
+  if (P < 1 || P > kMaxPermEx) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(null_examples_kernel, dim3(n_sub), dim3(256), 0, stream, table, P, sub_off,
+                     sub_rows, row_cand, cand_mom, y_mom, n, dx, dy, dz, k, feats, targ, obs);
+  return hipGetLastError();
+}
+
 // verdict: +1 include (t_obs clearly above the predicted 5% threshold), -1 stop (clearly
-// below), 0 borderline (run the surrogates).  Thresholds are predicted scaled by sqrt(N).
+// below), 0 borderline (run the surrogates).  The network predicts sqrt(N) * tau, so the
+// comparison is made on sqrt(N) * t_obs; s = |pred_0.01 - pred_0.05|.
 __global__ void gate_kernel(const float* __restrict__ pred, const double* __restrict__ obs, int n,
                             double margin_lo, double margin_hi, int* __restrict__ verdict) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double rn = sqrt((double)n);
-  const double t05 = (double)pred[0] / rn;
-  const double t01 = (double)pred[1] / rn;
-  const double s = fabs(t01 - t05);
-  const double t = obs[0];
+  const double t = sqrt((double)n) * obs[0];
+  const double t05 = (double)pred[0];
+  const double s = fabs((double)pred[1] - t05);
   *verdict = t > t05 + margin_hi * s ? 1 : (t < t05 - margin_lo * s ? -1 : 0);
+}
+
+// Per-feature mean and population standard deviation of feats [B][16] (FP64 accumulation, one
+// block per feature, fixed-order reduction); sd falls back to 1 for a constant feature.
+__global__ __launch_bounds__(256) void feature_norm_kernel(const float* __restrict__ feats, int64_t B,
+                                                           float* __restrict__ mu, float* __restrict__ sd) {
+  __shared__ double red[4];
+  const int f = blockIdx.x;
+  double s = 0.0;
+  for (int64_t r = threadIdx.x; r < B; r += blockDim.x) s += (double)feats[r * kNIn + f];
+  const double mean = block_sum(s, red) / (double)B;
+  double v = 0.0;
+  for (int64_t r = threadIdx.x; r < B; r += blockDim.x) {
+    const double d = (double)feats[r * kNIn + f] - mean;
+    v += d * d;
+  }
+  const double var = block_sum(v, red) / (double)B;
+  if (threadIdx.x == 0) {
+    mu[f] = (float)mean;
+    const float sdv = (float)sqrt(var);
+    sd[f] = sdv > 1e-12f ? sdv : 1.0f;
+  }
+}
+
+hipError_t launch_feature_norm(const float* feats, int64_t B, float* mu, float* sd, hipStream_t stream) {
+  hipLaunchKernelGGL(feature_norm_kernel, dim3(kNIn), dim3(256), 0, stream, feats, B, mu, sd);
+  return hipGetLastError();
 }
 
 hipError_t launch_gate(const float* pred, const double* obs, int n, double margin_lo, double margin_hi,

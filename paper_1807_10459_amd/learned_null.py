@@ -1,0 +1,75 @@
+"""Learned null for the greedy selection: training-set assembly, training and calibration.
+
+The threshold network predicts, from a step's 16 features, the step's surrogate
+max-statistic thresholds sqrt(N) * tau_0.05 and sqrt(N) * tau_0.01.  Its training examples
+come from the method itself: every greedy step run with surrogates yields a CMI table whose
+candidate subsets each have their own max-statistic null distribution (ksg_null_examples).
+select_parents then gates every step on the network and pays for the surrogates only when
+the observed statistic falls inside the calibrated margin around the predicted threshold;
+the plain permutation test stays the fallback and the judge.
+
+This module only sequences library calls (argument marshalling); the estimates, the
+example statistics, the features, training, standardisation and calibration all run in the
+library.  Randomness (which steps, conditioning sets and subsets) is supplied by the caller.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Iterable, List, Sequence
+
+from ._binding import Context, ThresholdNet
+
+
+@dataclasses.dataclass
+class StepSpec:
+    """One greedy step to draw examples from.
+
+    cand: device FP32 [C][N] candidate columns (ksg_embed layout); y: device FP32 [N];
+    pool: candidate indices tested in the step; cond: conditioning candidate indices;
+    perms: device int32 [P][N]; subsets: lists of positions into pool (each one example).
+    """
+
+    cand: object
+    y: object
+    pool: Sequence[int]
+    cond: Sequence[int]
+    perms: object
+    subsets: Sequence[Sequence[int]]
+    k: int = 4
+
+
+def examples_from_step(ctx: Context, spec: StepSpec):
+    """(feats [S][16], targets [S][2], obs [S][2]) device tensors for one step's subsets."""
+    table, _ = ctx.greedy_step(spec.cand, spec.y, spec.pool, spec.cond, spec.perms, k=spec.k)
+    return ctx.null_examples(table, list(spec.pool), spec.subsets, spec.cand, spec.y,
+                             dz=len(spec.cond), k=spec.k)
+
+
+def build_dataset(ctx: Context, specs: Iterable[StepSpec]):
+    """Concatenated examples of many steps, plus the step id of every example."""
+    import torch
+    fs, ts, os_, ids = [], [], [], []
+    for i, spec in enumerate(specs):
+        f, t, o = examples_from_step(ctx, spec)
+        fs.append(f)
+        ts.append(t)
+        os_.append(o)
+        ids.append(torch.full((f.shape[0],), i, dtype=torch.int32, device=f.device))
+    return torch.cat(fs), torch.cat(ts), torch.cat(os_), torch.cat(ids)
+
+
+def train_threshold_net(ctx: Context, feats, targets, init_params, epochs: int = 40,
+                        batch: int = 512, lr: float = 2e-3) -> tuple[ThresholdNet, List[float]]:
+    """Standardise on the training features, then Adam on the device; returns (net, loss history).
+
+    The rows are used in the order given: shuffle them beforehand.
+    """
+    net = ThresholdNet(ctx, init_params)
+    net.fit_norm(feats)
+    hist = net.train(feats, targets, epochs=epochs, batch=batch, lr=lr)
+    return net, [float(h) for h in hist]
+
+
+def calibrate(net: ThresholdNet, feats, obs, rate: float = 0.0025) -> dict:
+    """Gate margins on held-out examples so that at most rate of them are decided wrongly."""
+    return net.calibrate(feats, obs, rate)
