@@ -80,6 +80,158 @@ def cpu_baseline(cand, y, perms, order, sample_per_m=2, workers=None):
     return len(tasks) / wall, workers, desc, vals
 
 
+# ---------------------------------------------------------------------------------------------
+# Learned null: training set from seeded networks (seeds disjoint from the evaluation network)
+
+
+def _step_specs(ctx, torch, kind, seed, size, n_sub=64, device="cuda"):
+    """Greedy-step specifications for one seeded network (conditioning sets and subsets seeded)."""
+    import workloads
+    from paper_1807_10459_amd.learned_null import StepSpec
+    g = workloads.rng(seed + 50_000)
+    if kind == "ar2":
+        net = workloads.ar2_network(seed=seed, T=size + MAX_LAG, burn=500)
+        n_vars, P, m_max, steps = 5, 200, 8, 4
+        target = 0
+    else:
+        net = workloads.logistic_network(seed=seed, n_trials=size, T=3000)
+        n_vars, P, m_max, steps = 20, 500, 4, 3
+        target = int(g.integers(0, n_vars))
+    data = torch.from_numpy(net.data).to(device)
+    cand, y = ctx.embed(data, target=target, max_lag=MAX_LAG)
+    N = y.shape[0]
+    perms = torch.from_numpy(workloads.permutations(N, P, seed=seed + 60_000)).to(device)
+    C = n_vars * MAX_LAG
+    true = [src * MAX_LAG + lag - 1 for (src, tgt, lag) in net.edges if tgt == target]
+    true += [target * MAX_LAG, target * MAX_LAG + 1]
+    specs = []
+    for _ in range(steps):
+        m = int(g.integers(0, m_max + 1))
+        if g.random() < 0.5:
+            base = [c for c in true if c < C]
+            rest = [c for c in range(C) if c not in base]
+            order = base + [rest[i] for i in g.permutation(len(rest))]
+            cond = sorted(order[:m])
+        else:
+            cond = sorted(g.choice(C, m, replace=False).tolist())
+        pool = [c for c in range(C) if c not in cond]
+        subs = [list(range(len(pool)))]
+        for _ in range(n_sub - 1):
+            size_ = int(np.exp(g.uniform(0, np.log(len(pool)))))
+            subs.append(sorted(g.choice(len(pool), max(1, size_), replace=False).tolist()))
+        specs.append(StepSpec(cand, y, pool, cond, perms, subs))
+    return specs
+
+
+TRAIN_PLAN = ([("ar2", 1000 + i, n) for i, n in enumerate([2000] * 40 + [5000] * 24 + [10000] * 12)] +
+              [("logistic", 2000 + i, t) for i, t in enumerate([1] * 40 + [2] * 16 + [5] * 6 + [10] * 2)])
+
+
+def c4_dataset(ctx, plan, log=print):
+    import torch
+    from paper_1807_10459_amd.learned_null import build_dataset
+    parts = []
+    t0 = time.perf_counter()
+    for i, (kind, seed, size) in enumerate(plan):
+        parts.append(build_dataset(ctx, _step_specs(ctx, torch, kind, seed, size)))
+        if (i + 1) % 10 == 0:
+            log(f"dataset: {i + 1}/{len(plan)} networks, {sum(p[0].shape[0] for p in parts)} examples, "
+                f"{time.perf_counter() - t0:.1f} s")
+    feats = torch.cat([p[0] for p in parts])
+    targ = torch.cat([p[1] for p in parts])
+    obs = torch.cat([p[2] for p in parts])
+    net_id = torch.cat([torch.full((p[0].shape[0],), i, dtype=torch.int32, device=p[0].device)
+                        for i, p in enumerate(parts)])
+    return feats, targ, obs, net_id
+
+
+def c4_evaluate(ctx, args, log):
+    """Learned-null vs plain greedy selection on the 20-node logistic network (seed 3)."""
+    import torch
+    import workloads
+    from paper_1807_10459_amd.learned_null import calibrate, train_threshold_net
+    t0 = time.perf_counter()
+    feats, targ, obs, net_id = c4_dataset(ctx, TRAIN_PLAN, log=log)
+    t_data = time.perf_counter() - t0
+    held = (net_id % 7) == 3
+    tr = torch.nonzero(~held).flatten()
+    order = torch.from_numpy(workloads.permutations(tr.numel(), 1, seed=4242)[0].astype(np.int64)).cuda()
+    tr = tr[order]
+    t1 = time.perf_counter()
+    net, hist = train_threshold_net(ctx, feats[tr].contiguous(), targ[tr].contiguous(),
+                                    workloads.mlp_init(4243), epochs=60, batch=512, lr=2e-3)
+    t_train = time.perf_counter() - t1
+    hi_idx = torch.nonzero(held).flatten()
+    cal = calibrate(net, feats[hi_idx].contiguous(), obs[hi_idx].contiguous(), rate=0.0025)
+    log(f"dataset {feats.shape[0]} examples in {t_data:.1f} s; training {t_train:.1f} s "
+        f"(loss {hist[0]:.4f} -> {hist[-1]:.4f}); calibration {cal}")
+
+    net3 = workloads.logistic_network(seed=3)
+    data = torch.from_numpy(net3.data).cuda()
+    N = net3.data.shape[0] * (net3.data.shape[2] - MAX_LAG)
+    perms = torch.from_numpy(workloads.permutations(N, 500, seed=33)).cuda()
+    targets = [int(t) for t in args.targets.split(",")] if args.targets else list(range(20))
+    res = {}
+    for mode in ("plain", "learned"):
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        out = {}
+        for t in targets:
+            kw = dict(k=K, max_lag=MAX_LAG, alpha=0.05, omnibus=True)
+            if mode == "learned":
+                kw.update(learned=net, margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"])
+            else:  # the plain run also evaluates the gate on every step, for step agreement
+                kw.update(learned=net, margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"], judge=True)
+            out[t] = ctx.select_parents(data, t, perms, **kw)
+            log(f"{mode} target {t}: parents {out[t]['parents']} steps {out[t]['n_steps']} "
+                f"fallback {out[t]['n_fallback']} disagree {out[t]['n_disagree']} "
+                f"{time.perf_counter() - tm:.1f} s")
+        torch.cuda.synchronize()
+        res[mode] = (out, time.perf_counter() - tm)
+    plain, t_plain = res["plain"]
+    learned, t_learned = res["learned"]
+
+    def sources(r, t):  # final parent variables (omnibus-gated sources + target past)
+        vs = {v for (v, _) in r["parents"] if v == t}
+        if r["omnibus_tested"] and r["omnibus_significant"]:
+            vs |= {v for (v, _) in r["parents"] if v != t}
+        return vs
+    n_vars = 20
+    agree_pairs = sum(1 for t in targets for v in range(n_vars)
+                      if (v in sources(plain[t], t)) == (v in sources(learned[t], t)))
+    exact = sum(1 for t in targets if plain[t]["parents"] == learned[t]["parents"])
+    n_par_plain = sum(len(r["parents"]) for r in plain.values())
+    n_par_learned = sum(len(r["parents"]) for r in learned.values())
+    steps_judged = sum(r["n_steps"] for r in plain.values())
+    disagree = sum(r["n_disagree"] for r in plain.values())
+    true_edges = {(s_, t_) for (s_, t_, _) in net3.edges}
+    return {
+        "metric": "parents/sec learned vs plain null (20-node logistic network, N=29950, 500 surrogates)",
+        "value": round(n_par_learned / t_learned, 4),
+        "unit": "parents/s",
+        "plain_parents_per_s": round(n_par_plain / t_plain, 4),
+        "speedup": round((n_par_learned / t_learned) / max(n_par_plain / t_plain, 1e-12), 2),
+        "targets": targets,
+        "plain_seconds": round(t_plain, 2),
+        "learned_seconds": round(t_learned, 2),
+        "pair_agreement": agree_pairs / (len(targets) * n_vars),
+        "exact_parent_set_rate": exact / len(targets),
+        "step_agreement": 1.0 - disagree / max(steps_judged, 1),
+        "steps_judged": steps_judged,
+        "learned_fallback_steps": sum(r["n_fallback"] for r in learned.values()),
+        "learned_gate_steps": sum(r["n_gate_decided"] for r in learned.values()),
+        "learned_cmi": sum(r["n_cmi"] for r in learned.values()),
+        "plain_cmi": sum(r["n_cmi"] for r in plain.values()),
+        "calibration": cal,
+        "training": {"examples": int(feats.shape[0]), "held_out": int(hi_idx.numel()),
+                     "dataset_s": round(t_data, 1), "train_s": round(t_train, 1),
+                     "loss_first": hist[0], "loss_last": hist[-1]},
+        "true_source_edges_found_plain": sum(1 for t in targets for v in sources(plain[t], t)
+                                             if v != t and (v, t) in true_edges),
+        "true_source_edges": sum(1 for t in targets for (s_, t_) in true_edges if t_ == t),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +240,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--group-size", type=int, default=-1,
                     help="problems searched together (-1 tuned, 0 off, 8, 16)")
+    ap.add_argument("--workload", default="ar2", choices=["ar2", "c4"],
+                    help="ar2: CMI/s on the AR(2) forced path (default); c4: learned vs plain null")
+    ap.add_argument("--targets", default=None, help="c4: comma-separated targets (default all 20)")
+    ap.add_argument("--dump-dataset", default=None,
+                    help="build the learned-null training set and save it (npz) instead of benchmarking")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (a known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -100,6 +257,20 @@ def main():
     import torch
     import paper_1807_10459_amd as ksg
     import workloads
+
+    if args.workload == "c4":
+        ctx = ksg.Context(0)
+        line = c4_evaluate(ctx, args, log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps(line))
+        return
+
+    if args.dump_dataset:
+        ctx = ksg.Context(0)
+        f, t, o, nid = c4_dataset(ctx, TRAIN_PLAN, log=lambda m: print(m, file=sys.stderr, flush=True))
+        np.savez_compressed(args.dump_dataset, feats=f.cpu().numpy(), targ=t.cpu().numpy(),
+                            obs=o.cpu().numpy(), net_id=nid.cpu().numpy())
+        print(json.dumps({"dataset": args.dump_dataset, "examples": int(f.shape[0])}))
+        return
 
     net = workloads.ar2_network(seed=1)
     order = forced_order(net)

@@ -101,39 +101,43 @@ def test_calibration_matches_reference(lib, ctx):
     assert r["wrong"] <= 2 * int(0.005 * B) + 2
 
 
-def _dataset(lib, ctx, seeds, T, P, n_sub=48, m_max=3):
+def _dataset(lib, ctx, seeds, sizes, P=200, n_sub=64, m_max=8, steps=4):
     """Examples from greedy steps of seeded AR(2) networks (conditioning sets and subsets seeded)."""
     from paper_1807_10459_amd.learned_null import StepSpec, build_dataset
     specs = []
-    for s in seeds:
-        data = _net_data(s, T)
+    for s, n in zip(seeds, sizes):
+        data = _net_data(s, n + 5)
         g = workloads.rng(s + 5000)
         dcand, dy = ctx.embed(dev(data), target=0, max_lag=5)
         perms = dev(workloads.permutations(dy.shape[0], P, seed=s + 6000))
-        m = int(g.integers(0, m_max + 1))
-        cond = sorted(g.choice(25, m, replace=False).tolist())
-        pool = [c for c in range(25) if c not in cond]
-        subs = [list(range(len(pool)))]
-        for _ in range(n_sub - 1):
-            size = int(np.exp(g.uniform(0, np.log(len(pool)))))
-            subs.append(sorted(g.choice(len(pool), max(1, size), replace=False).tolist()))
-        specs.append(StepSpec(dcand.contiguous(), dy, pool, cond, perms, subs))
+        for _ in range(steps):
+            m = int(g.integers(0, m_max + 1))
+            cond = sorted(g.choice(25, m, replace=False).tolist())
+            pool = [c for c in range(25) if c not in cond]
+            subs = [list(range(len(pool)))]
+            for _ in range(n_sub - 1):
+                size = int(np.exp(g.uniform(0, np.log(len(pool)))))
+                subs.append(sorted(g.choice(len(pool), max(1, size), replace=False).tolist()))
+            specs.append(StepSpec(dcand, dy, pool, cond, perms, subs))
     return build_dataset(ctx, specs)
 
 
 def test_learned_gate_gain_over_table_and_select_parents(lib, ctx):
-    """Train on steps of seeded networks, calibrate on held-out steps, then (a) compare the
-    fraction of steps left to the surrogate test with a bucket-mean threshold table calibrated
-    the same way, and (b) run select_parents with the gate and the plain test as judge."""
+    """Train on steps of seeded networks, calibrate on held-out networks, then (a) compare the
+    fraction of held-out steps left to the surrogate test with that of a bucket-mean threshold
+    table calibrated the same way (the ablation: what the network gains), and (b) run
+    select_parents with the gate, judged by the plain test."""
     import torch
     from paper_1807_10459_amd.learned_null import calibrate, train_threshold_net
-    feats, targ, obs, _ = _dataset(lib, ctx, range(100, 148), T=805, P=99)
-    hf, ht, ho, _ = _dataset(lib, ctx, range(300, 316), T=805, P=99)
+    sizes = [1000, 2000] * 24
+    feats, targ, obs, _ = _dataset(lib, ctx, range(100, 148), sizes)
+    hf, ht, ho, _ = _dataset(lib, ctx, range(300, 312), [1000, 2000] * 6)
     order = torch.from_numpy(workloads.permutations(feats.shape[0], 1, seed=7)[0].astype(np.int64)).cuda()
     net, hist = train_threshold_net(ctx, feats[order].contiguous(), targ[order].contiguous(),
-                                    workloads.mlp_init(11), epochs=60, batch=256, lr=3e-3)
-    assert hist[-1] < 0.5 * hist[0]
-    cal = calibrate(net, hf, ho, rate=0.02)
+                                    workloads.mlp_init(11), epochs=60, batch=512, lr=2e-3)
+    assert hist[-1] < 0.25 * hist[0]
+    rate = 0.01
+    cal = calibrate(net, hf, ho, rate=rate)
     # baseline: mean thresholds per (log N, log c, d_z) bucket of the training set
     F, Tg = feats.cpu().numpy(), targ.cpu().numpy()
     HF, HO = hf.cpu().numpy(), ho.cpu().numpy()
@@ -145,16 +149,16 @@ def test_learned_gate_gain_over_table_and_select_parents(lib, ctx):
         table.setdefault(key(f), []).append(t)
     glob = Tg.mean(0)
     pred_tab = np.array([np.mean(table[key(f)], 0) if key(f) in table else glob for f in HF])
-    lo, hi = _calib_ref(pred_tab, HO, 0.02)
+    lo, hi = _calib_ref(pred_tab, HO, rate)
     s = np.maximum(np.abs(pred_tab[:, 1] - pred_tab[:, 0]), 1e-30)
     u = (HO[:, 0] - pred_tab[:, 0]) / s
     fallback_tab = float(np.mean((u <= hi) & (u >= -lo)))
-    print(f"fallback: network {cal['fallback']:.3f}, bucket table {fallback_tab:.3f}")
-    assert cal["fallback"] < fallback_tab
-    assert cal["fallback"] < 0.5
+    print(f"held-out fallback: network {cal['fallback']:.3f}, bucket table {fallback_tab:.3f}")
+    assert cal["fallback"] < 0.5 * fallback_tab
+    assert cal["wrong"] <= int(rate * HF.shape[0]) + 1
     # the gate in select_parents, judged by the plain test on every step
     data = _net_data(999, 2005)
-    perms = dev(workloads.permutations(2000, 99, seed=998))
+    perms = dev(workloads.permutations(2000, 200, seed=998))
     plain = ctx.select_parents(dev(data), 0, perms, k=4, max_lag=5)
     judged = ctx.select_parents(dev(data), 0, perms, k=4, max_lag=5, learned=net,
                                 margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"], judge=True)
@@ -163,6 +167,6 @@ def test_learned_gate_gain_over_table_and_select_parents(lib, ctx):
     learned = ctx.select_parents(dev(data), 0, perms, k=4, max_lag=5, learned=net,
                                  margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"])
     assert learned["n_fallback"] + learned["n_gate_decided"] == learned["n_steps"]
-    assert learned["n_cmi"] < plain["n_cmi"]
-    if learned["n_disagree"] == 0 and judged["n_disagree"] == 0:
+    assert learned["n_gate_decided"] >= 1 and learned["n_cmi"] < plain["n_cmi"]
+    if judged["n_disagree"] == 0:
         assert learned["parents"] == plain["parents"]
