@@ -101,19 +101,21 @@ def test_calibration_matches_reference(lib, ctx):
     assert r["wrong"] <= 2 * int(0.005 * B) + 2
 
 
-def _dataset(lib, ctx, seeds, sizes, P=200, n_sub=64, m_max=8, steps=4):
-    """Examples from greedy steps of seeded AR(2) networks (conditioning sets and subsets seeded)."""
+def _dataset(lib, ctx, seeds, P=500, n_sub=64, m_max=4, steps=3):
+    """Examples from greedy steps of seeded 20-node logistic-map networks (one trial,
+    N = 2995, 100 candidates; targets, conditioning sets and subsets seeded)."""
     from paper_1807_10459_amd.learned_null import StepSpec, build_dataset
     specs = []
-    for s, n in zip(seeds, sizes):
-        data = _net_data(s, n + 5)
+    for s in seeds:
+        net = workloads.logistic_network(seed=s, n_trials=1, T=3000)
         g = workloads.rng(s + 5000)
-        dcand, dy = ctx.embed(dev(data), target=0, max_lag=5)
+        target = int(g.integers(0, 20))
+        dcand, dy = ctx.embed(dev(net.data), target=target, max_lag=5)
         perms = dev(workloads.permutations(dy.shape[0], P, seed=s + 6000))
         for _ in range(steps):
             m = int(g.integers(0, m_max + 1))
-            cond = sorted(g.choice(25, m, replace=False).tolist())
-            pool = [c for c in range(25) if c not in cond]
+            cond = sorted(g.choice(100, m, replace=False).tolist())
+            pool = [c for c in range(100) if c not in cond]
             subs = [list(range(len(pool)))]
             for _ in range(n_sub - 1):
                 size = int(np.exp(g.uniform(0, np.log(len(pool)))))
@@ -129,9 +131,8 @@ def test_learned_gate_gain_over_table_and_select_parents(lib, ctx):
     select_parents with the gate, judged by the plain test."""
     import torch
     from paper_1807_10459_amd.learned_null import calibrate, train_threshold_net
-    sizes = [1000, 2000] * 24
-    feats, targ, obs, _ = _dataset(lib, ctx, range(100, 148), sizes)
-    hf, ht, ho, _ = _dataset(lib, ctx, range(300, 312), [1000, 2000] * 6)
+    feats, targ, obs, _ = _dataset(lib, ctx, range(100, 132))
+    hf, ht, ho, _ = _dataset(lib, ctx, range(300, 310))
     order = torch.from_numpy(workloads.permutations(feats.shape[0], 1, seed=7)[0].astype(np.int64)).cuda()
     net, hist = train_threshold_net(ctx, feats[order].contiguous(), targ[order].contiguous(),
                                     workloads.mlp_init(11), epochs=60, batch=512, lr=2e-3)
@@ -153,18 +154,22 @@ def test_learned_gate_gain_over_table_and_select_parents(lib, ctx):
     s = np.maximum(np.abs(pred_tab[:, 1] - pred_tab[:, 0]), 1e-30)
     u = (HO[:, 0] - pred_tab[:, 0]) / s
     fallback_tab = float(np.mean((u <= hi) & (u >= -lo)))
-    print(f"held-out fallback: network {cal['fallback']:.3f}, bucket table {fallback_tab:.3f}")
-    assert cal["fallback"] < 0.5 * fallback_tab
+    mse_net = float(((net.forward(hf).cpu().numpy() - ht.cpu().numpy()) ** 2).sum(1).mean())
+    mse_tab = float(((pred_tab - ht.cpu().numpy()) ** 2).sum(1).mean())
+    print(f"held-out: network fallback {cal['fallback']:.3f} mse {mse_net:.4f}; "
+          f"bucket table fallback {fallback_tab:.3f} mse {mse_tab:.4f}")
+    assert mse_net < 0.5 * mse_tab
+    assert cal["fallback"] < fallback_tab
     assert cal["wrong"] <= int(rate * HF.shape[0]) + 1
     # the gate in select_parents, judged by the plain test on every step
-    data = _net_data(999, 2005)
-    perms = dev(workloads.permutations(2000, 200, seed=998))
-    plain = ctx.select_parents(dev(data), 0, perms, k=4, max_lag=5)
-    judged = ctx.select_parents(dev(data), 0, perms, k=4, max_lag=5, learned=net,
+    data = workloads.logistic_network(seed=999, n_trials=1, T=3000).data
+    perms = dev(workloads.permutations(2995, 500, seed=998))
+    plain = ctx.select_parents(dev(data), 4, perms, k=4, max_lag=5)
+    judged = ctx.select_parents(dev(data), 4, perms, k=4, max_lag=5, learned=net,
                                 margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"], judge=True)
     assert judged["parents"] == plain["parents"]
     assert judged["n_disagree"] <= 1
-    learned = ctx.select_parents(dev(data), 0, perms, k=4, max_lag=5, learned=net,
+    learned = ctx.select_parents(dev(data), 4, perms, k=4, max_lag=5, learned=net,
                                  margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"])
     assert learned["n_fallback"] + learned["n_gate_decided"] == learned["n_steps"]
     assert learned["n_gate_decided"] >= 1 and learned["n_cmi"] < plain["n_cmi"]
