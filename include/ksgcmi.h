@@ -251,6 +251,15 @@ typedef struct ksg_parent_set {
   double omnibus_cmi;
   double omnibus_pval;
   int64_t n_cmi;        /* CMI estimates computed (originals + surrogates) */
+  /* Optional per-step log (host arrays of step_capacity entries, any may be NULL; steps beyond
+   * step_capacity are not logged): t_obs; the gate's predictions sqrt(N)*(tau_0.05, tau_0.01)
+   * ([step_capacity][2], NaN when no gate ran); the gate's verdict (+1 include, -1 stop,
+   * 0 borderline, 2 no gate); the plain test's decision (1 significant, 0 not, -1 not run). */
+  int32_t step_capacity;
+  double* step_tobs;
+  float* step_pred;
+  int32_t* step_verdict;
+  int32_t* step_plain;
 } ksg_parent_set;
 
 /* data: device FP32 [n_trials][n_vars][T].  out: host struct.

@@ -52,7 +52,9 @@ class _ParentSet(C.Structure):
                 ("cmi", C.c_void_p), ("pval", C.c_void_p), ("n_steps", C.c_int32),
                 ("n_fallback", C.c_int32), ("n_disagree", C.c_int32), ("n_gate_decided", C.c_int32),
                 ("omnibus_tested", C.c_int32), ("omnibus_significant", C.c_int32),
-                ("omnibus_cmi", C.c_double), ("omnibus_pval", C.c_double), ("n_cmi", C.c_int64)]
+                ("omnibus_cmi", C.c_double), ("omnibus_pval", C.c_double), ("n_cmi", C.c_int64),
+                ("step_capacity", C.c_int32), ("step_tobs", C.c_void_p), ("step_pred", C.c_void_p),
+                ("step_verdict", C.c_void_p), ("step_plain", C.c_void_p)]
 
 
 def _load():
@@ -284,7 +286,15 @@ class Context:
         lag = np.zeros(capacity, np.int32)
         cmi = np.zeros(capacity, np.float64)
         pv = np.zeros(capacity, np.float64)
+        scap = capacity + 1
+        s_t = np.zeros(scap, np.float64)
+        s_p = np.zeros((scap, 2), np.float32)
+        s_v = np.zeros(scap, np.int32)
+        s_pl = np.zeros(scap, np.int32)
         ps = _ParentSet(capacity, 0, var.ctypes.data, lag.ctypes.data, cmi.ctypes.data, pv.ctypes.data)
+        ps.step_capacity = scap
+        ps.step_tobs, ps.step_pred = s_t.ctypes.data, s_p.ctypes.data
+        ps.step_verdict, ps.step_plain = s_v.ctypes.data, s_pl.ctypes.data
         self._check(lib.select_parents(self._h, _ptr(data), n_vars, T, n_trials, int(target),
                                        C.byref(opts), C.byref(ps)), "select_parents")
         n = ps.n
@@ -294,7 +304,10 @@ class Context:
                     n_fallback=ps.n_fallback, n_disagree=ps.n_disagree,
                     n_gate_decided=ps.n_gate_decided, omnibus_tested=bool(ps.omnibus_tested),
                     omnibus_significant=bool(ps.omnibus_significant), omnibus_cmi=ps.omnibus_cmi,
-                    omnibus_pval=ps.omnibus_pval, n_cmi=ps.n_cmi)
+                    omnibus_pval=ps.omnibus_pval, n_cmi=ps.n_cmi,
+                    steps=[dict(t_obs=float(s_t[i]), pred=[float(s_p[i, 0]), float(s_p[i, 1])],
+                                verdict=int(s_v[i]), plain=int(s_pl[i]))
+                           for i in range(min(ps.n_steps, scap))])
 
     def null_examples(self, table, row_cand, subsets, cand, y, dz: int, k: int = 4):
         """Training examples from one step's surrogate table (see ksg_null_examples)."""

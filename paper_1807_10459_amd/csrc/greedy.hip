@@ -150,6 +150,8 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
     double t_obs = 0, pval = -1;
     int c_star = 0;
     bool run_full = true;
+    int gate_verdict = 2, plain_decision = -1;
+    float pred[2] = {NAN, NAN};
     if (o->learned) {
       // Originals only, then the gate on the device.
       st = s.step_cmis(0, 1, d_cmi);
@@ -157,8 +159,9 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
       out->n_cmi += cands;
       int verdict = 0;
       st = gate.decide(c, d_cmi, cands, s.P + 1, s.pool, 1, 1, (int)s.selected.size(), o->k, s.P,
-                       o->margin_lo, o->margin_hi, &verdict, &c_star, &t_obs);
+                       o->margin_lo, o->margin_hi, &verdict, &c_star, &t_obs, pred);
       if (st) return st;
+      gate_verdict = verdict;
       if (verdict != 0) {
         decision = verdict > 0 ? 1 : 0;
         run_full = o->judge != 0;
@@ -176,12 +179,23 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
       KSG_HIP(c, hipStreamSynchronize(c->stream));
       const MaxStatOut& m = c->h_ms[0];
       const int plain = m.significant ? 1 : 0;
+      plain_decision = plain;
       if (decision >= 0 && decision != plain) out->n_disagree++;
       if (decision >= 0 && o->judge) out->n_gate_decided++;
       decision = plain;
       t_obs = m.t_obs;
       pval = m.pval;
       c_star = m.c_star;
+    }
+    if (out->n_steps < out->step_capacity) {
+      const int i = out->n_steps;
+      if (out->step_tobs) out->step_tobs[i] = t_obs;
+      if (out->step_pred) {
+        out->step_pred[2 * i] = pred[0];
+        out->step_pred[2 * i + 1] = pred[1];
+      }
+      if (out->step_verdict) out->step_verdict[i] = gate_verdict;
+      if (out->step_plain) out->step_plain[i] = plain_decision;
     }
     out->n_steps++;
     if (decision != 1) break;

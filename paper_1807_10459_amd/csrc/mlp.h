@@ -77,12 +77,13 @@ struct LearnedGate {
     int verdict;
     int pad;
     double obs[2];
+    float pred[2];
   }* h = nullptr;  // pinned
   ~LearnedGate();
   int init(ksg_ctx* c, const ksg_mlp* m, const float* cand, int64_t n_pad, int C, const float* y, int n);
   int decide(ksg_ctx* c, const double* d_cmi, int cands, int stride, const std::vector<int>& pool,
              int dx, int dy, int dz, int k, int n_perm, double margin_lo, double margin_hi,
-             int* verdict, int* c_star, double* t_obs);
+             int* verdict, int* c_star, double* t_obs, float* pred);
 };
 
 }  // namespace ksg

@@ -306,7 +306,8 @@ int LearnedGate::init(ksg_ctx* c, const ksg_mlp* net, const float* cand, int64_t
 
 int LearnedGate::decide(ksg_ctx* c, const double* d_cmi, int cands, int stride,
                         const std::vector<int>& pool, int dx, int dy, int dz, int k, int n_perm,
-                        double margin_lo, double margin_hi, int* verdict, int* c_star, double* t_obs) {
+                        double margin_lo, double margin_hi, int* verdict, int* c_star, double* t_obs,
+                        float* pred) {
   KSG_HIP(c, hipMemcpyAsync(d_pool, pool.data(), sizeof(int32_t) * cands, hipMemcpyHostToDevice, c->stream));
   KSG_HIP(c, launch_step_features(d_cmi, stride, cands, d_pool, mom + (size_t)C * 3, mom, n, dx, dy, dz, k,
                                   n_perm, d_feat, d_obs, c->stream));
@@ -314,7 +315,10 @@ int LearnedGate::decide(ksg_ctx* c, const double* d_cmi, int cands, int stride,
   KSG_HIP(c, launch_gate(d_pred, d_obs, n, margin_lo, margin_hi, d_verdict, c->stream));
   KSG_HIP(c, hipMemcpyAsync(&h->verdict, d_verdict, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   KSG_HIP(c, hipMemcpyAsync(h->obs, d_obs, sizeof(double) * 2, hipMemcpyDeviceToHost, c->stream));
+  KSG_HIP(c, hipMemcpyAsync(h->pred, d_pred, sizeof(float) * 2, hipMemcpyDeviceToHost, c->stream));
   KSG_HIP(c, hipStreamSynchronize(c->stream));
+  pred[0] = h->pred[0];
+  pred[1] = h->pred[1];
   *verdict = h->verdict;
   *t_obs = h->obs[0];
   *c_star = (int)h->obs[1];

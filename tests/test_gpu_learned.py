@@ -112,9 +112,15 @@ def _dataset(lib, ctx, seeds, P=500, n_sub=64, m_max=4, steps=3):
         target = int(g.integers(0, 20))
         dcand, dy = ctx.embed(dev(net.data), target=target, max_lag=5)
         perms = dev(workloads.permutations(dy.shape[0], P, seed=s + 6000))
+        true = [src * 5 + lag - 1 for (src, tgt, lag) in net.edges if tgt == target]
+        true += [target * 5, target * 5 + 1]
         for _ in range(steps):
             m = int(g.integers(0, m_max + 1))
-            cond = sorted(g.choice(100, m, replace=False).tolist())
+            if g.random() < 0.5:  # conditioning on (a prefix of) the true parents and own past
+                rest = [c for c in range(100) if c not in true]
+                cond = sorted((true + [rest[i] for i in g.permutation(len(rest))])[:m])
+            else:
+                cond = sorted(g.choice(100, m, replace=False).tolist())
             pool = [c for c in range(100) if c not in cond]
             subs = [list(range(len(pool)))]
             for _ in range(n_sub - 1):
@@ -166,7 +172,10 @@ def test_learned_gate_gain_over_table_and_select_parents(lib, ctx):
     plain = ctx.select_parents(dev(data), 4, perms, k=4, max_lag=5)
     judged = ctx.select_parents(dev(data), 4, perms, k=4, max_lag=5, learned=net,
                                 margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"], judge=True)
+    for st in judged["steps"]:
+        print("judged step", st)
     assert judged["parents"] == plain["parents"]
+    assert all(st["plain"] in (0, 1) and st["verdict"] in (-1, 0, 1) for st in judged["steps"])
     assert judged["n_disagree"] <= 1
     learned = ctx.select_parents(dev(data), 4, perms, k=4, max_lag=5, learned=net,
                                  margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"])
