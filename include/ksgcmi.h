@@ -102,10 +102,13 @@ int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
 
 /* With KSG_OPT_TIMING on: device time of the search kernels (search + count + per-tile
  * digamma sums, finalisation excluded) summed over all launches since the last call, in
- * milliseconds, with their launch count and algorithmic operation count
- * (sum over problems of N(N-1)(4D+2), the brute-force FP32 op count: per ordered pair D
- * subtractions, D-1 maxima and 1 compare for the radius, the same plus 3 compares for the
- * counts).  Synchronises the stream; resets the accumulators.  Outputs are host pointers. */
+ * milliseconds, with their launch count and algorithmic FP32 operation count.  Problems
+ * searched alone count N(N-1)(4D+2) (per ordered pair D subtractions, D-1 maxima and 1
+ * compare for the radius, the same plus 3 compares for the counts).  A group of problems that
+ * share Y and Z counts the shared Y/Z work once per pair (2m+2 per pass, skip test included;
+ * 1 for the count pass when m = 0) plus, per problem, 3 (radius) and 5 (counts) operations on
+ * every pair of the reference steps the kernel did not skip (counted on the device).
+ * Synchronises the stream; resets the accumulators.  Outputs are host pointers. */
 int ksg_take_timing(ksg_ctx* ctx, double* ms, int64_t* launches, double* ops);
 
 /* ---------------------------------------------------------------------------

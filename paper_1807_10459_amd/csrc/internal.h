@@ -103,7 +103,7 @@ hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, in
                              hipStream_t stream);
 hipError_t launch_ksg_group(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
                             int n_items, const double* d_htab, double* d_partials, int m, int G,
-                            int kp, hipStream_t stream);
+                            int kp, unsigned long long* d_work, hipStream_t stream);
 hipError_t launch_interleave(const GroupDesc* d_gdesc, int n_groups, int max_pad, float* base,
                              hipStream_t stream);
 hipError_t launch_finalize(const ProbDesc* d_desc, int n_probs, const double* d_partials,

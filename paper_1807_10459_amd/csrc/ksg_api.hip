@@ -204,6 +204,7 @@ extern "C" void ksg_ctx_destroy(ksg_ctx* c) {
     if (b->ptr) (void)hipFree(b->ptr);
   if (c->d_counter) (void)hipFree(c->d_counter);
   if (c->d_ms) (void)hipFree(c->d_ms);
+  if (c->d_work) (void)hipFree(c->d_work);
   if (c->h_ms) (void)hipHostFree(c->h_ms);
   if (c->staging) (void)hipHostFree(c->staging);
   if (c->staging_done) (void)hipEventDestroy(c->staging_done);
@@ -225,7 +226,18 @@ extern "C" int ksg_ctx_set_option(ksg_ctx* c, int option, int64_t value) {
       c->group_size = (int)value;
       return KSG_OK;
     case KSG_OPT_USE_GRAPH: c->use_graph = value != 0; return KSG_OK;
-    case KSG_OPT_TIMING: c->timing = value != 0; return KSG_OK;
+    case KSG_OPT_TIMING:
+      c->timing = value != 0;
+      if (c->timing && !c->d_work) {
+        if (hipMalloc(&c->d_work, 2 * sizeof(unsigned long long)) != hipSuccess ||
+            hipMemset(c->d_work, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+          (void)hipGetLastError();
+          c->d_work = nullptr;
+          c->timing = false;
+          return c->fail(KSG_ENOMEM, "timing counters");
+        }
+      }
+      return KSG_OK;
     default: return c->fail(KSG_EINVAL, "unknown option %d", option);
   }
 }
@@ -587,7 +599,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     for (auto& kv : classes) {
       KSG_HIP(this, launch_ksg_group(pool_base, d_gdesc, d_items + gitem_off[ci], (int)group_items[ci].size(),
                                      (const double*)htab.ptr, (double*)partials.ptr, kv.first[0],
-                                     kv.first[1], kv.first[2], stream));
+                                     kv.first[1], kv.first[2], timing ? d_work : nullptr, stream));
       ++ci;
     }
   }
@@ -599,7 +611,9 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   if (timing) {
     KSG_HIP(this, hipEventRecord(t1, stream));
     timed.emplace_back(t0, t1);
-    for (int i = 0; i < np; ++i) timed_ops += algorithmic_ops(probs[i], group_of[i] >= 0 ? (int)groups[group_of[i]].size() : 1);
+    for (int i = 0; i < np; ++i)
+      if (group_of[i] < 0) timed_ops += algorithmic_ops(probs[i], 1);
+    for (size_t gi = 0; gi < groups.size(); ++gi) timed_ops += group_shared_ops(probs[groups[gi][0]]);
   }
   KSG_HIP(this, launch_finalize((const ProbDesc*)desc.ptr, np, (const double*)partials.ptr,
                                 (const double*)htab.ptr, d_out, stream));
@@ -608,18 +622,25 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   return KSG_OK;
 }
 
-// Algorithmic FP32 operations of one problem.  Ungrouped: the brute-force count over ordered
-// pairs, N(N-1)(4D+2) (radius: D sub, D-1 max, 1 compare; counts: D sub, D-1 max, 3 compares).
-// In a group of ng problems that share Y and Z, the Y/Z part of both passes is done once per
-// pair for the group, so each problem carries 1/ng of it: per pair, radius 1 sub + 1 max + 1
-// compare and counts 1 sub + 1 max + 3 compares per problem, plus (2(m+1) - 1) + (2(m+1) - 1)
-// shared sub/max operations (d^YZ for the radius; d^Z and d^YZ for the counts) divided by ng.
-double ksg_ctx::algorithmic_ops(const Problem& p, int ng) {
+// Algorithmic FP32 operations (the roofline's work count).
+// Ungrouped problem: the brute-force count over ordered pairs, N(N-1)(4D+2) (radius: D sub,
+// D-1 max, 1 compare; counts: D sub, D-1 max, 3 compares).
+// Grouped problems: the Y/Z part is done once per pair for the whole group -- radius pass
+// d^YZ (2m+1: m+1 sub, m max) and the skip test (1 compare); count pass d^Z and d^YZ (2m+1)
+// and the skip test (1) -- while the per-problem part, radius 3 (sub, max, compare) and
+// counts 5 (sub, max, 3 compares) per pair, is counted only over the reference steps that
+// the kernel did not skip (reported by the kernel in units of 4 references x 64 lanes).
+double ksg_ctx::algorithmic_ops(const Problem& p, int) {
   const double pairs = (double)p.n * (double)(p.n - 1);
-  const int D = p.dx + p.dy + p.dz;
-  if (ng <= 1) return pairs * (4.0 * D + 2.0);
-  const double shared = 2.0 * (2.0 * (p.dz + 1) - 1.0);
-  return pairs * (8.0 + shared / ng);
+  return pairs * (4.0 * (p.dx + p.dy + p.dz) + 2.0);
+}
+
+double ksg_ctx::group_shared_ops(const Problem& p) {
+  const double pairs = (double)p.n * (double)(p.n - 1);
+  const double m = p.dz;
+  const double pass1 = 2.0 * m + 1.0 + 1.0;
+  const double pass2 = p.dz > 0 ? 2.0 * m + 1.0 + 1.0 : 1.0;
+  return pairs * (pass1 + pass2);
 }
 
 // Finite check over the destinations (first n rows) of the given jobs; synchronises.
@@ -776,9 +797,14 @@ extern "C" int ksg_take_timing(ksg_ctx* c, double* ms, int64_t* launches, double
     c->event_pool.push_back(pr.first);
     c->event_pool.push_back(pr.second);
   }
+  unsigned long long w[2] = {0, 0};
+  if (c->d_work) {
+    KSG_HIP(c, hipMemcpy(w, c->d_work, sizeof w, hipMemcpyDeviceToHost));
+    KSG_HIP(c, hipMemset(c->d_work, 0, sizeof w));
+  }
   *ms = total;
   *launches = (int64_t)c->timed.size();
-  *ops = c->timed_ops;
+  *ops = c->timed_ops + 256.0 * (3.0 * (double)w[0] + 5.0 * (double)w[1]);
   c->timed.clear();
   c->timed_ops = 0.0;
   return KSG_OK;

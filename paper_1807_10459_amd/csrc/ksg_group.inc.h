@@ -31,7 +31,8 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
                                            const KSG_AS4 GroupDesc* gd, int tile,
                                            const double* __restrict__ htab,
                                            double* __restrict__ partials,
-                                           double (*s_red)[G]) {
+                                           double (*s_red)[G],
+                                           unsigned long long* __restrict__ work) {
   constexpr int U = 4;
   constexpr int W = M + 1;
   const int n = gd->n;
@@ -66,7 +67,13 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
 #pragma unroll
     for (int i = 0; i < KP; ++i) b[g][i] = (i < KP - 1 - k) ? -INFINITY : INFINITY;
 
+  // Exact step skip: d(g) = max(|dx_g|, dyz) >= dyz, so when dyz >= max_g radius_g for all
+  // four references and every lane of the wave, no problem can gain a neighbour and the
+  // per-problem work of the step is skipped.  bmax_g holds that maximum per lane.
+  unsigned bmax = __float_as_uint(INFINITY);
+  unsigned done1 = 0;  // steps whose per-problem work ran (wave-uniform)
   for (int s = 0; s < steps; ++s) {
+    // the step's X block is requested first so that its latency overlaps the Y/Z work
     ksg_f4 rx[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) rx[g] = px[s * G + g];
@@ -80,6 +87,10 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
       dyz[2] = fmaxf(dyz[2], fabsf(rz.z - qz[a]));
       dyz[3] = fmaxf(dyz[3], fabsf(rz.w - qz[a]));
     }
+    const unsigned dmin = min(min(__float_as_uint(dyz[0]), __float_as_uint(dyz[1])),
+                              min(__float_as_uint(dyz[2]), __float_as_uint(dyz[3])));
+    if (__builtin_amdgcn_ballot_w64(dmin < bmax) == 0) continue;
+    ++done1;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       float d[U];
@@ -94,15 +105,24 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
         for (int u = 0; u < U; ++u) topk_insert<KP>(b[g], d[u]);
       }
     }
+    bmax = __float_as_uint(b[0][KP - 1]);
+#pragma unroll
+    for (int g = 1; g < G; ++g) bmax = max(bmax, __float_as_uint(b[g][KP - 1]));
   }
   float eps[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) eps[g] = b[g][KP - 1];
 
   // ---- pass 2: strict counts, self included ----
+  // Exact step skip: every count needs d^Z < eps_g (d^XZ and d^YZ are >= d^Z), so a step in
+  // which d^Z >= max_g eps_g for all references and lanes contributes nothing.
   unsigned cxz[G], cyz[G], cz[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) cxz[g] = cyz[g] = cz[g] = 0u;
+  unsigned emax = __float_as_uint(eps[0]);
+#pragma unroll
+  for (int g = 1; g < G; ++g) emax = max(emax, __float_as_uint(eps[g]));
+  unsigned done2 = 0;
   for (int s = 0; s < steps; ++s) {
     const ksg_f4 ry = pyz[s * W];
     float dz[U], dyz[U];
@@ -120,6 +140,9 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
         dz[2] = fmaxf(dz[2], fabsf(rz.z - qz[a]));
         dz[3] = fmaxf(dz[3], fabsf(rz.w - qz[a]));
       }
+      const unsigned zmin = min(min(__float_as_uint(dz[0]), __float_as_uint(dz[1])),
+                                min(__float_as_uint(dz[2]), __float_as_uint(dz[3])));
+      if (__builtin_amdgcn_ballot_w64(zmin < emax) == 0) continue;
       dyz[0] = fmaxf(fabsf(ry.x - qy), dz[0]);
       dyz[1] = fmaxf(fabsf(ry.y - qy), dz[1]);
       dyz[2] = fmaxf(fabsf(ry.z - qy), dz[2]);
@@ -131,6 +154,7 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
       dyz[2] = fabsf(ry.z - qy);
       dyz[3] = fabsf(ry.w - qy);
     }
+    ++done2;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       const ksg_f4 rx = px[s * G + g];
@@ -158,6 +182,11 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
     t = wave_sum(t);
     if ((threadIdx.x & 63) == 0) s_red[wave][g] = t;
   }
+  if (work && (threadIdx.x & 63) == 0) {
+    // per-problem work units executed by this wave: (steps run) x (problems in the group)
+    atomicAdd(&work[0], (unsigned long long)done1 * (unsigned)ng);
+    atomicAdd(&work[1], (unsigned long long)done2 * (unsigned)ng);
+  }
   __syncthreads();
   if ((int)threadIdx.x < ng)
     partials[gd->part_base + threadIdx.x * gd->n_tiles + tile] =
@@ -170,14 +199,15 @@ __global__ __launch_bounds__(kTileQ) void ksg_group_kernel(const float* __restri
                                                            const GroupDesc* __restrict__ descs,
                                                            const WorkItem* __restrict__ items,
                                                            const double* __restrict__ htab,
-                                                           double* __restrict__ partials) {
+                                                           double* __restrict__ partials,
+                                                           unsigned long long* __restrict__ work) {
   __shared__ double s_red[kTileQ / 64][G];
   const KSG_AS4 WorkItem* i4 = (const KSG_AS4 WorkItem*)items;
   const int grp = i4[blockIdx.x].prob;
   if (grp < 0) return;
   const int tile = i4[blockIdx.x].tile;
   const KSG_AS4 GroupDesc* gd = (const KSG_AS4 GroupDesc*)descs + grp;
-  group_tile<M, G, KP>(base, gd, tile, htab, partials, s_red);
+  group_tile<M, G, KP>(base, gd, tile, htab, partials, s_red, work);
 }
 
 }  // namespace ksg

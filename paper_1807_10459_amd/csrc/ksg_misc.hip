@@ -217,7 +217,7 @@ hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, in
 
 hipError_t launch_ksg_group(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
                             int n_items, const double* d_htab, double* d_partials, int m, int G,
-                            int kp, hipStream_t stream) {
+                            int kp, unsigned long long* d_work, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
   if (m < 0 || m > 14 || (G != 8 && G != 16) || (kp != 5 && kp != 9)) return hipErrorInvalidValue;
   const void* const* table = kp == 5 ? (G == 8 ? group_kernels_kp5_g8 : group_kernels_kp5_g16)
@@ -227,7 +227,8 @@ hipError_t launch_ksg_group(const float* base, const GroupDesc* d_gdesc, const W
   const WorkItem* a2 = d_items;
   const double* a3 = d_htab;
   double* a4 = d_partials;
-  void* args[] = {&a0, &a1, &a2, &a3, &a4};
+  unsigned long long* a5 = d_work;
+  void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5};
   return hipLaunchKernel(table[m], dim3(n_items), dim3(kTileQ), args, 0, stream);
 }
 

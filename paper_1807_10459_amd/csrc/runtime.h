@@ -68,6 +68,8 @@ struct ksg_ctx {
     return t ? t : 16;
   }
   static double algorithmic_ops(const ksg::Problem& p, int ng);
+  static double group_shared_ops(const ksg::Problem& p);
+  unsigned long long* d_work = nullptr;  // grouped-kernel work counters (timing mode)
 
   // KSG_OPT_TIMING: events around each search launch, harvested by ksg_take_timing.
   bool timing = false;
