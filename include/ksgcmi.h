@@ -100,6 +100,13 @@ typedef enum ksg_option {
 } ksg_option;
 int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
 
+/* Roofline calibration: instructions per second x 64 lanes ("lane operations") of one VALU
+ * instruction class on the context's device, from 16 independent chains per lane with no
+ * memory traffic: kind 0 v_sub_f32, 1 v_max3_f32 (|.| operands), 2 v_cmp_lt_f32 + v_addc
+ * (a compare-and-count, two instructions), 3 v_med3_f32, 4 v_fma_f32.  Synchronises.
+ * Errors: KSG_EINVAL, KSG_EDEVICE. */
+int ksg_valu_probe(ksg_ctx* ctx, int32_t kind, int32_t iters, double* lane_ops_per_s);
+
 /* With KSG_OPT_TIMING on: device time of the search kernels (search + count + per-tile
  * digamma sums, finalisation excluded) summed over all launches since the last call, in
  * milliseconds, with their launch count and algorithmic FP32 operation count.  Problems

@@ -72,6 +72,7 @@ def _load():
         "ksg_ctx_destroy": ([vp], None),
         "ksg_last_error": ([vp], C.c_char_p),
         "ksg_ctx_set_option": ([vp, i32, i64], i32),
+        "ksg_valu_probe": ([vp, i32, i32, C.POINTER(d)], i32),
         "ksg_take_timing": ([vp, C.POINTER(d), C.POINTER(i64), C.POINTER(d)], i32),
         "cmi_ksg": ([vp, vp, vp, vp, i64, vp, i32, C.POINTER(d)], i32),
         "cmi_ksg_batch": ([vp, C.POINTER(_Problem), i32, vp], i32),
@@ -208,6 +209,12 @@ class Context:
 
     def set_option(self, option: int, value: int):
         self._check(lib.ksg_ctx_set_option(self._h, option, int(value)), "ksg_ctx_set_option")
+
+    def valu_probe(self, kind: int, iters: int = 4096) -> float:
+        """Lane operations per second of one VALU instruction class (see ksg_valu_probe)."""
+        r = C.c_double()
+        self._check(lib.ksg_valu_probe(self._h, int(kind), int(iters), C.byref(r)), "ksg_valu_probe")
+        return r.value
 
     def take_timing(self):
         """(search-kernel milliseconds, launches, algorithmic FP32 ops) since the last call."""

@@ -24,6 +24,7 @@ SOURCES = [
     "greedy.hip",
     "mlp_kernels.hip",
     "mlp_api.hip",
+    "valu_probe.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

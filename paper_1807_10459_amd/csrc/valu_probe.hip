@@ -1,0 +1,77 @@
+// VALU throughput probe: the issue rate of the instruction classes the search kernels use,
+// measured on the running device, so that the roofline peak is a measurement of this part
+// rather than a datasheet reading.  Each lane runs 16 independent chains of one instruction
+// class; no memory traffic inside the timed loop.
+#include <hip/hip_runtime.h>
+
+#include "../../include/ksgcmi.h"
+#include "runtime.h"
+
+namespace ksg {
+
+template <int KIND>
+__global__ __launch_bounds__(256) void valu_probe_kernel(int iters, float seed, float* __restrict__ out) {
+  float a[16];
+  unsigned c[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    a[i] = seed + (float)(threadIdx.x + i);
+    c[i] = threadIdx.x + i;
+  }
+  const float s = seed * 0.5f;
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if constexpr (KIND == 0) {  // FP32 subtract
+        asm volatile("v_sub_f32 %0, %0, %1" : "+v"(a[i]) : "v"(s));
+      } else if constexpr (KIND == 1) {  // FP32 max3 with |.| modifiers
+        asm volatile("v_max3_f32 %0, |%0|, |%1|, %0" : "+v"(a[i]) : "v"(s));
+      } else if constexpr (KIND == 2) {  // FP32 compare to a mask + add-with-carry count
+        asm volatile("v_cmp_lt_f32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, 0, %0, vcc"
+                     : "+v"(c[i]) : "v"(a[i]), "v"(s) : "vcc");
+      } else if constexpr (KIND == 3) {  // FP32 median of three
+        asm volatile("v_med3_f32 %0, %0, %1, %0" : "+v"(a[i]) : "v"(s));
+      } else {  // FP32 fused multiply-add (the datasheet's operation)
+        asm volatile("v_fma_f32 %0, %0, %1, %1" : "+v"(a[i]) : "v"(s));
+      }
+    }
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc += a[i] + (float)c[i];
+  if (acc == 12345.678f) out[threadIdx.x] = acc;  // keeps the chains live
+}
+
+}  // namespace ksg
+
+using namespace ksg;
+
+extern "C" int ksg_valu_probe(ksg_ctx* c, int32_t kind, int32_t iters, double* lane_ops_per_s) {
+  if (!c) return KSG_EINVAL;
+  if (!lane_ops_per_s || kind < 0 || kind > 4 || iters < 1) return c->fail(KSG_EINVAL, "ksg_valu_probe: bad argument");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(KSG_EDEVICE, "hipSetDevice");
+  const void* fns[5] = {(const void*)&valu_probe_kernel<0>, (const void*)&valu_probe_kernel<1>,
+                        (const void*)&valu_probe_kernel<2>, (const void*)&valu_probe_kernel<3>,
+                        (const void*)&valu_probe_kernel<4>};
+  const int blocks = c->cus * 16;
+  int st = c->reserve(c->tmp, 256 * sizeof(float), "probe output");
+  if (st) return st;
+  float seed = 1.25f;
+  float* out = (float*)c->tmp.ptr;
+  void* args[] = {&iters, &seed, &out};
+  hipEvent_t e0 = c->get_event(), e1 = c->get_event();
+  if (!e0 || !e1) return c->fail(KSG_EDEVICE, "events");
+  hipError_t e = hipLaunchKernel(fns[kind], dim3(blocks), dim3(256), args, 0, c->stream);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+  if (e == hipSuccess) e = hipLaunchKernel(fns[kind], dim3(blocks), dim3(256), args, 0, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  c->event_pool.push_back(e0);
+  c->event_pool.push_back(e1);
+  if (e != hipSuccess) return c->hip_fail(e, "valu probe");
+  const double per_lane = (double)iters * 16.0 * (kind == 2 ? 2.0 : 1.0);
+  *lane_ops_per_s = per_lane * 256.0 * (double)blocks / (ms * 1e-3);
+  return KSG_OK;
+}
