@@ -58,6 +58,9 @@ class _ParentSet(C.Structure):
 
 
 def _load():
+    # The HIP runtime is process-wide: load PyTorch's first so that the library and the
+    # tensors it is handed share one runtime instance.
+    import torch  # noqa: F401
     if not os.path.exists(lib_path):
         raise ImportError(f"{lib_path} is missing: build it with __graft_entry__.build() "
                           "(hipcc --offload-arch=gfx950)")
