@@ -103,7 +103,9 @@ int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
 /* Roofline calibration: instructions per second x 64 lanes ("lane operations") of one VALU
  * instruction class on the context's device, from 16 independent chains per lane with no
  * memory traffic: kind 0 v_sub_f32, 1 v_max3_f32 (|.| operands), 2 v_cmp_lt_f32 + v_addc
- * (a compare-and-count, two instructions), 3 v_med3_f32, 4 v_fma_f32.  Synchronises.
+ * (a compare-and-count, two instructions), 3 v_med3_f32, 4 v_fma_f32, 5 v_max_f32, 6
+ * v_max_f32 with |.| (VOP3), 7 v_min_u32, 8 v_cndmask_b32, 9 v_add_u32, 10 v_cmp_lt_f32 into an
+ * SGPR pair, 11 v_and_b32, 12 v_sub_f32 with an SGPR operand, 13 v_min3_f32.  Synchronises.
  * Errors: KSG_EINVAL, KSG_EDEVICE. */
 int ksg_valu_probe(ksg_ctx* ctx, int32_t kind, int32_t iters, double* lane_ops_per_s);
 

@@ -22,17 +22,35 @@ __global__ __launch_bounds__(256) void valu_probe_kernel(int iters, float seed, 
   for (int it = 0; it < iters; ++it) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      if constexpr (KIND == 0) {  // FP32 subtract
+      if constexpr (KIND == 0) {  // FP32 subtract (VOP2)
         asm volatile("v_sub_f32 %0, %0, %1" : "+v"(a[i]) : "v"(s));
-      } else if constexpr (KIND == 1) {  // FP32 max3 with |.| modifiers
+      } else if constexpr (KIND == 1) {  // FP32 max3 with |.| modifiers (VOP3)
         asm volatile("v_max3_f32 %0, |%0|, |%1|, %0" : "+v"(a[i]) : "v"(s));
-      } else if constexpr (KIND == 2) {  // FP32 compare to a mask + add-with-carry count
+      } else if constexpr (KIND == 2) {  // FP32 compare to VCC + add-with-carry count (VOPC + VOP2)
         asm volatile("v_cmp_lt_f32 vcc, %1, %2\n\tv_addc_co_u32 %0, vcc, 0, %0, vcc"
                      : "+v"(c[i]) : "v"(a[i]), "v"(s) : "vcc");
-      } else if constexpr (KIND == 3) {  // FP32 median of three
+      } else if constexpr (KIND == 3) {  // FP32 median of three (VOP3)
         asm volatile("v_med3_f32 %0, %0, %1, %0" : "+v"(a[i]) : "v"(s));
-      } else {  // FP32 fused multiply-add (the datasheet's operation)
+      } else if constexpr (KIND == 4) {  // FP32 fused multiply-add (VOP3)
         asm volatile("v_fma_f32 %0, %0, %1, %1" : "+v"(a[i]) : "v"(s));
+      } else if constexpr (KIND == 5) {  // FP32 max (VOP2, no modifiers)
+        asm volatile("v_max_f32 %0, %0, %1" : "+v"(a[i]) : "v"(s));
+      } else if constexpr (KIND == 6) {  // FP32 max with |.| (VOP3 encoding)
+        asm volatile("v_max_f32_e64 %0, |%0|, %1" : "+v"(a[i]) : "v"(s));
+      } else if constexpr (KIND == 7) {  // u32 min (VOP2)
+        asm volatile("v_min_u32 %0, %0, %1" : "+v"(c[i]) : "v"(c[0]));
+      } else if constexpr (KIND == 8) {  // select by VCC (VOP2)
+        asm volatile("v_cndmask_b32 %0, %0, %1, vcc" : "+v"(a[i]) : "v"(s));
+      } else if constexpr (KIND == 9) {  // u32 add (VOP2)
+        asm volatile("v_add_u32 %0, %0, %1" : "+v"(c[i]) : "v"(c[0]));
+      } else if constexpr (KIND == 10) {  // FP32 compare into an SGPR pair (VOP3)
+        asm volatile("v_cmp_lt_f32_e64 s[40:41], %0, %1" : : "v"(a[i]), "v"(s) : "s40", "s41");
+      } else if constexpr (KIND == 11) {  // bitwise and (VOP2)
+        asm volatile("v_and_b32 %0, %0, %1" : "+v"(c[i]) : "v"(c[0]));
+      } else if constexpr (KIND == 12) {  // FP32 subtract with an SGPR operand (VOP2)
+        asm volatile("v_sub_f32 %0, %1, %0" : "+v"(a[i]) : "s"(seed));
+      } else {  // FP32 min3 (VOP3)
+        asm volatile("v_min3_f32 %0, %0, %1, %0" : "+v"(a[i]) : "v"(s));
       }
     }
   }
@@ -48,11 +66,15 @@ using namespace ksg;
 
 extern "C" int ksg_valu_probe(ksg_ctx* c, int32_t kind, int32_t iters, double* lane_ops_per_s) {
   if (!c) return KSG_EINVAL;
-  if (!lane_ops_per_s || kind < 0 || kind > 4 || iters < 1) return c->fail(KSG_EINVAL, "ksg_valu_probe: bad argument");
+  if (!lane_ops_per_s || kind < 0 || kind > 13 || iters < 1) return c->fail(KSG_EINVAL, "ksg_valu_probe: bad argument");
   if (hipSetDevice(c->device) != hipSuccess) return c->fail(KSG_EDEVICE, "hipSetDevice");
-  const void* fns[5] = {(const void*)&valu_probe_kernel<0>, (const void*)&valu_probe_kernel<1>,
-                        (const void*)&valu_probe_kernel<2>, (const void*)&valu_probe_kernel<3>,
-                        (const void*)&valu_probe_kernel<4>};
+  const void* fns[14] = {(const void*)&valu_probe_kernel<0>,  (const void*)&valu_probe_kernel<1>,
+                         (const void*)&valu_probe_kernel<2>,  (const void*)&valu_probe_kernel<3>,
+                         (const void*)&valu_probe_kernel<4>,  (const void*)&valu_probe_kernel<5>,
+                         (const void*)&valu_probe_kernel<6>,  (const void*)&valu_probe_kernel<7>,
+                         (const void*)&valu_probe_kernel<8>,  (const void*)&valu_probe_kernel<9>,
+                         (const void*)&valu_probe_kernel<10>, (const void*)&valu_probe_kernel<11>,
+                         (const void*)&valu_probe_kernel<12>, (const void*)&valu_probe_kernel<13>};
   const int blocks = c->cus * 16;
   int st = c->reserve(c->tmp, 256 * sizeof(float), "probe output");
   if (st) return st;
