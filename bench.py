@@ -84,58 +84,44 @@ def cpu_baseline(cand, y, perms, order, sample_per_m=2, workers=None):
 # Learned null: training set from seeded networks (seeds disjoint from the evaluation network)
 
 
-def _step_specs(ctx, torch, kind, seed, size, n_sub=64, device="cuda"):
-    """Greedy-step specifications for one seeded network (conditioning sets and subsets seeded)."""
-    import workloads
-    from paper_1807_10459_amd.learned_null import StepSpec
-    g = workloads.rng(seed + 50_000)
-    if kind == "ar2":
-        net = workloads.ar2_network(seed=seed, T=size + MAX_LAG, burn=500)
-        n_vars, P, m_max, steps = 5, 200, 8, 4
-        target = 0
-    else:
-        net = workloads.logistic_network(seed=seed, n_trials=size, T=3000)
-        n_vars, P, m_max, steps = 20, 500, 4, 3
-        target = int(g.integers(0, n_vars))
-    data = torch.from_numpy(net.data).to(device)
-    cand, y = ctx.embed(data, target=target, max_lag=MAX_LAG)
-    N = y.shape[0]
-    perms = torch.from_numpy(workloads.permutations(N, P, seed=seed + 60_000)).to(device)
-    C = n_vars * MAX_LAG
-    true = [src * MAX_LAG + lag - 1 for (src, tgt, lag) in net.edges if tgt == target]
-    true += [target * MAX_LAG, target * MAX_LAG + 1]
-    specs = []
-    for _ in range(steps):
-        m = int(g.integers(0, m_max + 1))
-        if g.random() < 0.5:
-            base = [c for c in true if c < C]
-            rest = [c for c in range(C) if c not in base]
-            order = base + [rest[i] for i in g.permutation(len(rest))]
-            cond = sorted(order[:m])
-        else:
-            cond = sorted(g.choice(C, m, replace=False).tolist())
-        pool = [c for c in range(C) if c not in cond]
-        subs = [list(range(len(pool)))]
-        for _ in range(n_sub - 1):
-            size_ = int(np.exp(g.uniform(0, np.log(len(pool)))))
-            subs.append(sorted(g.choice(len(pool), max(1, size_), replace=False).tolist()))
-        specs.append(StepSpec(cand, y, pool, cond, perms, subs))
-    return specs
+# (kind, seed, size): ar2 -> N; logistic -> trials of 3000 samples.  Seeds are disjoint from
+# the evaluation network (logistic seed 3).
+TRAIN_PLAN = ([("ar2", 1000 + i, n) for i, n in enumerate([2000] * 30 + [5000] * 16 + [10000] * 8)] +
+              [("logistic", 2000 + i, t) for i, t in enumerate([1] * 40 + [2] * 12 + [5] * 4 + [10] * 1)])
 
 
-TRAIN_PLAN = ([("ar2", 1000 + i, n) for i, n in enumerate([2000] * 40 + [5000] * 24 + [10000] * 12)] +
-              [("logistic", 2000 + i, t) for i, t in enumerate([1] * 40 + [2] * 16 + [5] * 6 + [10] * 2)])
+def _subsets_for(g):
+    def f(n_pool, step):
+        subs = [list(range(n_pool))]
+        for _ in range(47):
+            size = int(np.exp(g.uniform(0, np.log(n_pool))))
+            subs.append(sorted(g.choice(n_pool, max(1, size), replace=False).tolist()))
+        return subs
+    return f
 
 
 def c4_dataset(ctx, plan, log=print):
+    """Training examples from the plain greedy paths of seeded networks (one target each)."""
     import torch
-    from paper_1807_10459_amd.learned_null import build_dataset
+    import workloads
+    from paper_1807_10459_amd.learned_null import greedy_path_examples
     parts = []
     t0 = time.perf_counter()
     for i, (kind, seed, size) in enumerate(plan):
-        parts.append(build_dataset(ctx, _step_specs(ctx, torch, kind, seed, size)))
-        if (i + 1) % 10 == 0:
-            log(f"dataset: {i + 1}/{len(plan)} networks, {sum(p[0].shape[0] for p in parts)} examples, "
+        g = workloads.rng(seed + 50_000)
+        if kind == "ar2":
+            net = workloads.ar2_network(seed=seed, T=size + MAX_LAG, burn=500)
+            P, target = 200, 0
+        else:
+            net = workloads.logistic_network(seed=seed, n_trials=size, T=3000)
+            P, target = 500, int(g.integers(0, 20))
+        data = torch.from_numpy(net.data).cuda()
+        cand, y = ctx.embed(data, target=target, max_lag=MAX_LAG)
+        perms = torch.from_numpy(workloads.permutations(y.shape[0], P, seed=seed + 60_000)).cuda()
+        f, t, o, steps, _ = greedy_path_examples(ctx, cand, y, perms, _subsets_for(g), k=K)
+        parts.append((f, t, o))
+        if (i + 1) % 10 == 0 or i + 1 == len(plan):
+            log(f"dataset: {i + 1}/{len(plan)} paths, {sum(p[0].shape[0] for p in parts)} examples, "
                 f"{time.perf_counter() - t0:.1f} s")
     feats = torch.cat([p[0] for p in parts])
     targ = torch.cat([p[1] for p in parts])

@@ -58,6 +58,38 @@ def build_dataset(ctx: Context, specs: Iterable[StepSpec]):
     return torch.cat(fs), torch.cat(ts), torch.cat(os_), torch.cat(ids)
 
 
+def greedy_path_examples(ctx: Context, cand, y, perms, subsets_for, k: int = 4,
+                         alpha: float = 0.05, max_cond: int = 14):
+    """Examples from every step of the plain greedy selection on one target.
+
+    The plain method is run step by step (ksg_greedy_step: all candidates x surrogates in one
+    batched launch, then the max-statistic test), so the examples come from exactly the
+    steps -- conditioning sets, candidate pools, observed statistics -- that select_parents
+    meets.  subsets_for(n_pool, step) returns the candidate subsets (positions into the pool)
+    to take from each step; the caller owns the randomness.
+    Returns (feats, targets, obs, n_steps, parents).
+    """
+    import torch
+    C = cand.shape[0]
+    pool = list(range(C))
+    cond: List[int] = []
+    fs, ts, os_ = [], [], []
+    step = 0
+    while pool and len(cond) <= max_cond:
+        table, res = ctx.greedy_step(cand, y, pool, cond, perms, k=k, alpha=alpha)
+        f, t, o = ctx.null_examples(table, pool, subsets_for(len(pool), step), cand, y, dz=len(cond), k=k)
+        fs.append(f)
+        ts.append(t)
+        os_.append(o)
+        step += 1
+        if not res["significant"]:
+            break
+        c = pool[res["c_star"]]
+        cond.append(c)
+        pool.remove(c)
+    return torch.cat(fs), torch.cat(ts), torch.cat(os_), step, cond
+
+
 def train_threshold_net(ctx: Context, feats, targets, init_params, epochs: int = 40,
                         batch: int = 512, lr: float = 2e-3) -> tuple[ThresholdNet, List[float]]:
     """Standardise on the training features, then Adam on the device; returns (net, loss history).
