@@ -137,7 +137,11 @@ def c4_evaluate(ctx, args, log):
     import workloads
     from paper_1807_10459_amd.learned_null import calibrate, train_threshold_net
     t0 = time.perf_counter()
-    feats, targ, obs, net_id = c4_dataset(ctx, TRAIN_PLAN, log=log)
+    if args.dataset:  # a training set written earlier by --dump-dataset (same recipe)
+        d = np.load(args.dataset)
+        feats, targ, obs, net_id = (torch.from_numpy(d[k]).cuda() for k in ("feats", "targ", "obs", "net_id"))
+    else:
+        feats, targ, obs, net_id = c4_dataset(ctx, TRAIN_PLAN, log=log)
     t_data = time.perf_counter() - t0
     held = (net_id % 7) == 3
     tr = torch.nonzero(~held).flatten()
@@ -229,6 +233,7 @@ def main():
     ap.add_argument("--workload", default="ar2", choices=["ar2", "c4"],
                     help="ar2: CMI/s on the AR(2) forced path (default); c4: learned vs plain null")
     ap.add_argument("--targets", default=None, help="c4: comma-separated targets (default all 20)")
+    ap.add_argument("--dataset", default=None, help="c4: load the training set from this npz")
     ap.add_argument("--dump-dataset", default=None,
                     help="build the learned-null training set and save it (npz) instead of benchmarking")
     ap.add_argument("--copy-calibration", action="store_true",
