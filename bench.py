@@ -270,6 +270,9 @@ def main():
     data = torch.from_numpy(net.data).cuda()
     perms = torch.from_numpy(perms_np).cuda()
     ctx = ksg.Context(0)
+    t_tune = time.perf_counter()
+    tuned = ctx.autotune(8192) if args.group_size == -1 else None
+    t_tune = time.perf_counter() - t_tune
     ctx.set_option(ctx.OPT_GROUP_SIZE, args.group_size)
     tables = {m: torch.empty((25 - m, N_PERM + 1), dtype=torch.float64, device="cuda") for m in FORCED_M}
 
@@ -334,6 +337,8 @@ def main():
                                f"{n_cmi} CMIs per step",
                    "n_cmi_per_step": n_cmi},
         "roofline": roofline,
+        "autotune": {"group_size_k4_by_m": tuned["k<=4"] if tuned else None,
+                     "seconds": round(t_tune, 3)},
     }
 
     if args.copy_calibration:

@@ -100,6 +100,15 @@ typedef enum ksg_option {
 } ksg_option;
 int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
 
+/* Autotuner of the grouped search kernel: for k <= 4 and k <= 8 and every conditioning
+ * dimension m = 0..14, time the group sizes 8 and 16 on a synthetic batch (32 problems of n
+ * points sharing Y and Z) and keep the faster for KSG_OPT_GROUP_SIZE = -1.  cache_path (host
+ * string or NULL): a text file of per-device results (keyed by architecture, compute units
+ * and library version); an existing entry is used instead of timing, a new one is appended.
+ * tuned_out (host int32 [30] or NULL): the chosen sizes, k <= 4 first.  Synchronises.
+ * Errors: KSG_EINVAL (n outside [256, 2^20]), KSG_ENOMEM, KSG_EDEVICE. */
+int ksg_autotune(ksg_ctx* ctx, int64_t n, const char* cache_path, int32_t* tuned_out);
+
 /* Roofline calibration: instructions per second x 64 lanes ("lane operations") of one VALU
  * instruction class on the context's device, from 16 independent chains per lane with no
  * memory traffic: kind 0 v_sub_f32, 1 v_max3_f32 (|.| operands), 2 v_cmp_lt_f32 + v_addc

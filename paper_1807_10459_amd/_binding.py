@@ -75,6 +75,7 @@ def _load():
         "ksg_ctx_destroy": ([vp], None),
         "ksg_last_error": ([vp], C.c_char_p),
         "ksg_ctx_set_option": ([vp, i32, i64], i32),
+        "ksg_autotune": ([vp, i64, C.c_char_p, vp], i32),
         "ksg_valu_probe": ([vp, i32, i32, C.POINTER(d)], i32),
         "ksg_take_timing": ([vp, C.POINTER(d), C.POINTER(i64), C.POINTER(d)], i32),
         "cmi_ksg": ([vp, vp, vp, vp, i64, vp, i32, C.POINTER(d)], i32),
@@ -212,6 +213,13 @@ class Context:
 
     def set_option(self, option: int, value: int):
         self._check(lib.ksg_ctx_set_option(self._h, option, int(value)), "ksg_ctx_set_option")
+
+    def autotune(self, n: int = 8192, cache_path: Optional[str] = None):
+        """Pick the group size per (k bucket, m) by timing (see ksg_autotune); returns the table."""
+        out = np.zeros(30, np.int32)
+        self._check(lib.ksg_autotune(self._h, int(n), cache_path.encode() if cache_path else None,
+                                     out.ctypes.data), "ksg_autotune")
+        return {"k<=4": out[:15].tolist(), "k<=8": out[15:].tolist()}
 
     def valu_probe(self, kind: int, iters: int = 4096) -> float:
         """Lane operations per second of one VALU instruction class (see ksg_valu_probe)."""

@@ -25,6 +25,7 @@ SOURCES = [
     "mlp_kernels.hip",
     "mlp_api.hip",
     "valu_probe.hip",
+    "autotune.hip",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -17,11 +17,6 @@
 
 using namespace ksg;
 
-#define KSG_HIP(ctx, expr)                                   \
-  do {                                                       \
-    hipError_t e_ = (expr);                                  \
-    if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #expr); \
-  } while (0)
 
 static int64_t round_up64(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 

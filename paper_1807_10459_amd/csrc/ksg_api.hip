@@ -35,11 +35,6 @@ int ksg_ctx::hip_fail(hipError_t e, const char* what) {
               hipGetErrorString(e));
 }
 
-#define KSG_HIP(ctx, expr)                                 \
-  do {                                                     \
-    hipError_t e_ = (expr);                                \
-    if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #expr); \
-  } while (0)
 
 // ============================================================== device buffers
 

@@ -14,11 +14,6 @@
 
 using namespace ksg;
 
-#define KSG_HIP(ctx, expr)                                   \
-  do {                                                       \
-    hipError_t e_ = (expr);                                  \
-    if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #expr); \
-  } while (0)
 
 #define KSG_HIP_RAW(expr)                    \
   do {                                       \

@@ -37,6 +37,14 @@ struct Problem {
 
 void ksg_build_harmonic(int64_t nmax, double* out);
 
+// Return a ksg_status from the enclosing function when a HIP call fails.
+#define KSG_HIP(ctx, expr)                                   \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #expr); \
+  } while (0)
+
+
 struct ksg_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -65,7 +73,7 @@ struct ksg_ctx {
   int64_t last_groups = 0;
   int tuned_group_size(int m, int k) const {
     const int t = tuned_g[k <= 4 ? 0 : 1][m < 15 ? m : 14];
-    return t ? t : 16;
+    return t ? t : 8;
   }
   static double algorithmic_ops(const ksg::Problem& p, int ng);
   static double group_shared_ops(const ksg::Problem& p);

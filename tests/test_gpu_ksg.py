@@ -262,3 +262,12 @@ def test_many_groups_xcd_order(lib, ctx):
         x = cands[c] if q == 0 else cands[c][perms[q - 1]]
         ref = ksg_cmi(x, p.y, p.z, 4)
         assert abs(ref_all[idx] - ref) <= tol(ref)
+
+
+def test_autotune_table_and_cache(lib, ctx, tmp_path):
+    path = str(tmp_path / "tune.txt")
+    a = ctx.autotune(2048, cache_path=path)
+    assert all(g in (8, 16) for g in a["k<=4"] + a["k<=8"]) and len(a["k<=4"]) == 15
+    b = ctx.autotune(2048, cache_path=path)  # served from the cache
+    assert a == b
+    assert open(path).read().count("\n") == 1
