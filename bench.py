@@ -222,6 +222,22 @@ def c4_evaluate(ctx, args, log):
     }
 
 
+def _traffic_record():
+    """HBM bytes per grouped-search launch from the committed counter record, or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "ksg_group_kernel_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = b"".join(open(os.path.join(ROOT, "paper_1807_10459_amd", "csrc", f), "rb").read()
+                       for f in ("ksg_group.inc.h", "ksg_search.inc.h"))
+        if hashlib.sha256(src).hexdigest() == rec["kernel_source_sha256"]:
+            return rec["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        pass
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,7 +326,7 @@ def main():
         "peak": round(PEAK_VALU / 1e12, 3),
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_VALU, 4),
-        "traffic": None,
+        "traffic": _traffic_record() if args.group_size != 0 else None,
         "kernel": "ksg_group_kernel (k-NN radius + strict counts + digamma partial sums, "
                   "Y/Z distances shared by each group of candidates/surrogates)" if args.group_size != 0
                   else "ksg_batch_kernel (k-NN radius + strict counts + digamma partial sums)",
