@@ -120,9 +120,8 @@ def c4_dataset(ctx, plan, log=print):
         perms = torch.from_numpy(workloads.permutations(y.shape[0], P, seed=seed + 60_000)).cuda()
         f, t, o, steps, _ = greedy_path_examples(ctx, cand, y, perms, _subsets_for(g), k=K)
         parts.append((f, t, o))
-        if (i + 1) % 10 == 0 or i + 1 == len(plan):
-            log(f"dataset: {i + 1}/{len(plan)} paths, {sum(p[0].shape[0] for p in parts)} examples, "
-                f"{time.perf_counter() - t0:.1f} s")
+        log(f"dataset: {i + 1}/{len(plan)} paths, {sum(p[0].shape[0] for p in parts)} examples, "
+            f"{time.perf_counter() - t0:.1f} s")
     feats = torch.cat([p[0] for p in parts])
     targ = torch.cat([p[1] for p in parts])
     obs = torch.cat([p[2] for p in parts])
