@@ -35,6 +35,11 @@ struct alignas(16) ProbDesc {
 //   X block  [n_pad/4][G][4]   (G = the kernel's group size; unused slots repeat column 0)
 //   YZ block [n_pad/4][m+1][4] (Y first), shared by every group with the same Y and Z and
 //   written by the group with write_yz = 1.
+// Both blocks hold the rows in ascending order of the key column (Z_1, or Y when m = 0):
+// block row r is source row sigma[r], sigma at sigma_off (int32, n_pad entries, written once
+// per Y/Z set; rows n..n_pad-1 map to themselves).  The estimate is a sum over all rows, so
+// the order does not change it; it lets a wave of neighbouring queries bound its search to
+// a window of the key column.
 // Problem g of the group writes its per-tile partial sums at part_base + g * n_tiles + tile.
 constexpr int kGroupMax = 16;
 struct alignas(16) GroupDesc {
@@ -49,8 +54,10 @@ struct alignas(16) GroupDesc {
   int32_t n_tiles;
   int32_t part_base;
   int32_t write_yz;
-  int32_t pad_[2];
+  uint32_t sigma_off;
+  int32_t pad_;
 };
+static_assert(sizeof(GroupDesc) % 16 == 0, "GroupDesc is copied as an array of 16-byte aligned records");
 
 // Work item: one query tile of one problem (or group); prob < 0 marks an empty slot.
 struct WorkItem {
@@ -104,6 +111,8 @@ hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, in
 hipError_t launch_ksg_group(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
                             int n_items, const double* d_htab, double* d_partials, int m, int G,
                             int kp, unsigned long long* d_work, hipStream_t stream);
+hipError_t launch_key_order(const GroupDesc* d_gdesc, int n_groups, int max_pad, float* base,
+                            hipStream_t stream);
 hipError_t launch_interleave(const GroupDesc* d_gdesc, int n_groups, int max_pad, float* base,
                              hipStream_t stream);
 hipError_t launch_finalize(const ProbDesc* d_desc, int n_probs, const double* d_partials,

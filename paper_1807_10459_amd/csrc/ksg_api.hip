@@ -224,8 +224,8 @@ extern "C" int ksg_ctx_set_option(ksg_ctx* c, int option, int64_t value) {
     case KSG_OPT_TIMING:
       c->timing = value != 0;
       if (c->timing && !c->d_work) {
-        if (hipMalloc(&c->d_work, 2 * sizeof(unsigned long long)) != hipSuccess ||
-            hipMemset(c->d_work, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        if (hipMalloc(&c->d_work, 3 * sizeof(unsigned long long)) != hipSuccess ||
+            hipMemset(c->d_work, 0, 3 * sizeof(unsigned long long)) != hipSuccess) {
           (void)hipGetLastError();
           c->d_work = nullptr;
           c->timing = false;
@@ -392,10 +392,10 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     }
   }
   // Interleaved blocks of the groups follow the packed columns in the same pool.
-  std::vector<int64_t> xi_off(groups.size()), yzi_off(groups.size());
+  std::vector<int64_t> xi_off(groups.size()), yzi_off(groups.size()), sigma_off(groups.size());
   std::vector<int> write_yz(groups.size(), 0);
   {
-    std::map<std::vector<int64_t>, int64_t> yz_sets;
+    std::map<std::vector<int64_t>, std::pair<int64_t, int64_t>> yz_sets;  // block, key order
     for (size_t gi = 0; gi < groups.size(); ++gi) {
       const int i0 = groups[gi][0];
       const int64_t n_pad = round_up(probs[i0].n, kPad);
@@ -405,11 +405,15 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       for (int a = 1; a < 2 + probs[i0].dz; ++a) key.push_back(col_off[i0][a]);
       auto it = yz_sets.find(key);
       if (it == yz_sets.end()) {
-        it = yz_sets.emplace(key, pool_floats).first;
+        const int64_t block = pool_floats;
         pool_floats += (int64_t)(probs[i0].dz + 1) * n_pad;
+        const int64_t order = pool_floats;  // int32 row indices, one per padded row
+        pool_floats += n_pad;
+        it = yz_sets.emplace(key, std::make_pair(block, order)).first;
         write_yz[gi] = 1;
       }
-      yzi_off[gi] = it->second;
+      yzi_off[gi] = it->second.first;
+      sigma_off[gi] = it->second.second;
     }
   }
   if (!groups.empty() && pool_floats > (int64_t)UINT32_MAX)
@@ -508,6 +512,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     gd.xi_off = (uint32_t)xi_off[gi];
     gd.yzi_off = (uint32_t)yzi_off[gi];
     gd.write_yz = write_yz[gi];
+    gd.sigma_off = (uint32_t)sigma_off[gi];
     gd.G = group_size_of[gi];
     gd.n = (int)p0.n;
     gd.n_pad = (int)round_up(p0.n, kPad);
@@ -579,8 +584,10 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     if (st) return st;
   }
   const GroupDesc* d_gdesc = (const GroupDesc*)((char*)desc.ptr + sz_desc);
-  if (!groups.empty())
+  if (!groups.empty()) {
+    KSG_HIP(this, launch_key_order(d_gdesc, (int)groups.size(), max_pad, pool_base, stream));
     KSG_HIP(this, launch_interleave(d_gdesc, (int)groups.size(), max_pad, pool_base, stream));
+  }
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (timing) {
     t0 = get_event();
@@ -608,7 +615,6 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     timed.emplace_back(t0, t1);
     for (int i = 0; i < np; ++i)
       if (group_of[i] < 0) timed_ops += algorithmic_ops(probs[i], 1);
-    for (size_t gi = 0; gi < groups.size(); ++gi) timed_ops += group_shared_ops(probs[groups[gi][0]]);
   }
   KSG_HIP(this, launch_finalize((const ProbDesc*)desc.ptr, np, (const double*)partials.ptr,
                                 (const double*)htab.ptr, d_out, stream));
@@ -620,22 +626,15 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
 // Algorithmic FP32 operations (the roofline's work count).
 // Ungrouped problem: the brute-force count over ordered pairs, N(N-1)(4D+2) (radius: D sub,
 // D-1 max, 1 compare; counts: D sub, D-1 max, 3 compares).
-// Grouped problems: the Y/Z part is done once per pair for the whole group -- radius pass
-// d^YZ (2m+1: m+1 sub, m max) and the skip test (1 compare); count pass d^Z and d^YZ (2m+1)
-// and the skip test (1) -- while the per-problem part, radius 3 (sub, max, compare) and
-// counts 5 (sub, max, 3 compares) per pair, is counted only over the reference steps that
-// the kernel did not skip (reported by the kernel in units of 4 references x 64 lanes).
+// Grouped problems are counted by the kernel itself, over the reference steps it executed
+// (units of 4 references x 64 lanes): the Y/Z part once per pair for the whole group --
+// radius pass d^YZ (2m+1: m+1 sub, m max) and the skip test (1 compare); count pass d^Z and
+// d^YZ (2m+1) and the skip test (1), or 1 when m = 0 -- and the per-problem part, radius 3
+// (sub, max, compare) and counts 5 (sub, max, 3 compares) per pair, for every problem whose
+// step was not skipped.  Steps outside a wave's key window are not executed and not counted.
 double ksg_ctx::algorithmic_ops(const Problem& p, int) {
   const double pairs = (double)p.n * (double)(p.n - 1);
   return pairs * (4.0 * (p.dx + p.dy + p.dz) + 2.0);
-}
-
-double ksg_ctx::group_shared_ops(const Problem& p) {
-  const double pairs = (double)p.n * (double)(p.n - 1);
-  const double m = p.dz;
-  const double pass1 = 2.0 * m + 1.0 + 1.0;
-  const double pass2 = p.dz > 0 ? 2.0 * m + 1.0 + 1.0 : 1.0;
-  return pairs * (pass1 + pass2);
 }
 
 // Finite check over the destinations (first n rows) of the given jobs; synchronises.
@@ -792,14 +791,14 @@ extern "C" int ksg_take_timing(ksg_ctx* c, double* ms, int64_t* launches, double
     c->event_pool.push_back(pr.first);
     c->event_pool.push_back(pr.second);
   }
-  unsigned long long w[2] = {0, 0};
+  unsigned long long w[3] = {0, 0, 0};
   if (c->d_work) {
     KSG_HIP(c, hipMemcpy(w, c->d_work, sizeof w, hipMemcpyDeviceToHost));
     KSG_HIP(c, hipMemset(c->d_work, 0, sizeof w));
   }
   *ms = total;
   *launches = (int64_t)c->timed.size();
-  *ops = c->timed_ops + 256.0 * (3.0 * (double)w[0] + 5.0 * (double)w[1]);
+  *ops = c->timed_ops + 256.0 * (3.0 * (double)w[0] + 5.0 * (double)w[1] + (double)w[2]);
   c->timed.clear();
   c->timed_ops = 0.0;
   return KSG_OK;

@@ -8,10 +8,12 @@
 //   joint  d_ij(g)    = max(|x_g,j - x_g,i|, d^YZ_ij)          (pass 1: radius eps_i(g))
 //   counts d^XZ_ij(g) = max(|x_g,j - x_g,i|, d^Z_ij)           (pass 2: n_XZ, n_YZ, n_Z)
 // Every distance, radius and count is bit-identical to the single-problem kernel (the same
-// FP32 subtractions and exact maxima, only evaluated once instead of G times), so the
-// estimates are unchanged.  Column data come from one device pool through 32-bit offsets
-// held in SGPRs; references arrive through the scalar data path as in the single-problem
-// kernel.
+// FP32 subtractions and exact maxima, only evaluated once instead of G times).  The rows are
+// searched in the order of a key column, which bounds each wave's scan to a window of rows
+// (below) without changing any radius or count; only the order in which the FP64 per-point
+// terms are summed differs from the single-problem kernel.  Column data come from one device
+// pool through 32-bit offsets held in SGPRs; references arrive through the scalar data path
+// as in the single-problem kernel.
 #pragma once
 
 #include "ksg_search.inc.h"
@@ -56,6 +58,23 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
   for (int a = 0; a < M; ++a) qz[a] = yzi[(qs * W + 1 + a) * 4 + ql];
   const int steps = n_pad / U;
 
+  // Key window.  The rows are in ascending order of the key column (Z_1, or Y when m = 0),
+  // and the 64 queries of a wave are consecutive rows.  Every distance of the search is at
+  // least |k_j - k_i| (a coordinate difference in the max norm), and because FP32 rounding
+  // is monotone, fl(k_j - k_i) >= fl(k_b - k_i) for every row j beyond a boundary row b on
+  // the far side of the query.  So once the first key of a step to the right (the last key
+  // of a step to the left) is at least a lane's bound away from that lane's key, for every
+  // lane, no later step in that direction can change the wave's results: the scan in that
+  // direction ends there.  The wave scans its own rows first, then alternates right and
+  // left (pass 1, so that the radii shrink early), or right then left (pass 2).
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int w0 = tile * kTileQ + wave * 64;
+  const bool live = w0 < n;
+  const int s_lo = live ? (w0 >> 2) : 0;
+  const int s_hi = live ? (min(w0 + 63, n - 1) >> 2) : -1;
+  constexpr int KC = M > 0 ? 1 : 0;  // key column in the YZ block
+  const float qkey = M > 0 ? qz[0] : qy;
+
   // ---- pass 1: (k+1) smallest joint distances per problem, self included ----
   // max(|t|, dyz) is taken as med3(|t|, dyz, +inf) and the "any candidate below the radius"
   // test as an unsigned minimum of the (non-negative) distance bit patterns: neither form
@@ -67,55 +86,89 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
 #pragma unroll
     for (int i = 0; i < KP; ++i) b[g][i] = (i < KP - 1 - k) ? -INFINITY : INFINITY;
 
-  // Exact step skip: d(g) = max(|dx_g|, dyz) >= dyz, so when dyz >= max_g radius_g for all
-  // four references and every lane of the wave, no problem can gain a neighbour and the
-  // per-problem work of the step is skipped.  bmax_g holds that maximum per lane.
+  // Exact skips: d(g) = max(|dx_g|, dyz) >= dyz, so when dyz >= radius_g for all four
+  // references and every lane of the wave, problem g cannot gain a neighbour in the step;
+  // when that holds for bmax = max_g radius_g the whole step is skipped.
   unsigned bmax = __float_as_uint(INFINITY);
-  unsigned done1 = 0;  // steps whose per-problem work ran (wave-uniform)
-  for (int s = 0; s < steps; ++s) {
-    // the step's X block is requested first so that its latency overlaps the Y/Z work
-    ksg_f4 rx[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g) rx[g] = px[s * G + g];
-    const ksg_f4 ry = pyz[s * W];
-    float dyz[U] = {fabsf(ry.x - qy), fabsf(ry.y - qy), fabsf(ry.z - qy), fabsf(ry.w - qy)};
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-      const ksg_f4 rz = pyz[s * W + 1 + a];
-      dyz[0] = fmaxf(dyz[0], fabsf(rz.x - qz[a]));
-      dyz[1] = fmaxf(dyz[1], fabsf(rz.y - qz[a]));
-      dyz[2] = fmaxf(dyz[2], fabsf(rz.z - qz[a]));
-      dyz[3] = fmaxf(dyz[3], fabsf(rz.w - qz[a]));
-    }
-    const unsigned dmin = min(min(__float_as_uint(dyz[0]), __float_as_uint(dyz[1])),
-                              min(__float_as_uint(dyz[2]), __float_as_uint(dyz[3])));
-    if (__builtin_amdgcn_ballot_w64(dmin < bmax) == 0) continue;
-    ++done1;
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      float d[U];
-      d[0] = __builtin_amdgcn_fmed3f(fabsf(rx[g].x - qx[g]), dyz[0], INFINITY);
-      d[1] = __builtin_amdgcn_fmed3f(fabsf(rx[g].y - qx[g]), dyz[1], INFINITY);
-      d[2] = __builtin_amdgcn_fmed3f(fabsf(rx[g].z - qx[g]), dyz[2], INFINITY);
-      d[3] = __builtin_amdgcn_fmed3f(fabsf(rx[g].w - qx[g]), dyz[3], INFINITY);
-      const unsigned lo = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
-                              min(__float_as_uint(d[2]), __float_as_uint(d[3])));
-      if (lo < __float_as_uint(b[g][KP - 1])) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) topk_insert<KP>(b[g], d[u]);
+  unsigned done1 = 0;   // problem-steps whose per-problem work ran (wave-uniform)
+  unsigned shared = 0;  // shared-part operations / 256 (wave-uniform)
+  {
+    int own = s_lo, r = s_hi + 1, l = s_lo - 1;
+    bool ract = live && r < steps, lact = live && l >= 0, right_turn = true;
+    for (;;) {
+      int s, dir;
+      if (own <= s_hi) {
+        s = own++;
+        dir = 0;
+      } else if (ract && (right_turn || !lact)) {
+        s = r;
+        dir = 1;
+      } else if (lact) {
+        s = l;
+        dir = -1;
+      } else {
+        break;
       }
-    }
-    bmax = __float_as_uint(b[0][KP - 1]);
+      // the step's X block is requested first so that its latency overlaps the Y/Z work
+      ksg_f4 rx[G];
 #pragma unroll
-    for (int g = 1; g < G; ++g) bmax = max(bmax, __float_as_uint(b[g][KP - 1]));
+      for (int g = 0; g < G; ++g) rx[g] = px[s * G + g];
+      const ksg_f4 ry = pyz[s * W];
+      if (dir != 0) {
+        const ksg_f4 rk = pyz[s * W + KC];
+        const float gap = dir > 0 ? rk.x - qkey : qkey - rk.w;
+        if (__builtin_amdgcn_ballot_w64(__float_as_uint(gap) < bmax) == 0) {
+          if (dir > 0) ract = false;
+          else lact = false;
+          continue;
+        }
+        if (dir > 0) ract = ++r < steps;
+        else lact = --l >= 0;
+        right_turn = !right_turn;
+      }
+      shared += 2 * M + 2;
+      float dyz[U] = {fabsf(ry.x - qy), fabsf(ry.y - qy), fabsf(ry.z - qy), fabsf(ry.w - qy)};
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        const ksg_f4 rz = pyz[s * W + 1 + a];
+        dyz[0] = fmaxf(dyz[0], fabsf(rz.x - qz[a]));
+        dyz[1] = fmaxf(dyz[1], fabsf(rz.y - qz[a]));
+        dyz[2] = fmaxf(dyz[2], fabsf(rz.z - qz[a]));
+        dyz[3] = fmaxf(dyz[3], fabsf(rz.w - qz[a]));
+      }
+      const unsigned dmin = min(min(__float_as_uint(dyz[0]), __float_as_uint(dyz[1])),
+                                min(__float_as_uint(dyz[2]), __float_as_uint(dyz[3])));
+      if (__builtin_amdgcn_ballot_w64(dmin < bmax) == 0) continue;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (__builtin_amdgcn_ballot_w64(dmin < __float_as_uint(b[g][KP - 1])) == 0) continue;
+        done1 += g < ng ? 1u : 0u;
+        float d[U];
+        d[0] = __builtin_amdgcn_fmed3f(fabsf(rx[g].x - qx[g]), dyz[0], INFINITY);
+        d[1] = __builtin_amdgcn_fmed3f(fabsf(rx[g].y - qx[g]), dyz[1], INFINITY);
+        d[2] = __builtin_amdgcn_fmed3f(fabsf(rx[g].z - qx[g]), dyz[2], INFINITY);
+        d[3] = __builtin_amdgcn_fmed3f(fabsf(rx[g].w - qx[g]), dyz[3], INFINITY);
+        const unsigned lo = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
+                                min(__float_as_uint(d[2]), __float_as_uint(d[3])));
+        if (lo < __float_as_uint(b[g][KP - 1])) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) topk_insert<KP>(b[g], d[u]);
+        }
+      }
+      bmax = __float_as_uint(b[0][KP - 1]);
+#pragma unroll
+      for (int g = 1; g < G; ++g) bmax = max(bmax, __float_as_uint(b[g][KP - 1]));
+    }
   }
   float eps[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) eps[g] = b[g][KP - 1];
 
   // ---- pass 2: strict counts, self included ----
-  // Exact step skip: every count needs d^Z < eps_g (d^XZ and d^YZ are >= d^Z), so a step in
-  // which d^Z >= max_g eps_g for all references and lanes contributes nothing.
+  // Every count needs d^Z < eps_g (d^XZ and d^YZ are >= d^Z): a step in which d^Z >= eps_g
+  // for all references and lanes contributes nothing to problem g, and with d^Z >= |dk| the
+  // key window bounds the scan exactly.  Without Z (m = 0) the X counts are not bounded by
+  // the key (Y), and the scan covers every row.
   unsigned cxz[G], cyz[G], cz[G];
 #pragma unroll
   for (int g = 0; g < G; ++g) cxz[g] = cyz[g] = cz[g] = 0u;
@@ -123,55 +176,92 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
 #pragma unroll
   for (int g = 1; g < G; ++g) emax = max(emax, __float_as_uint(eps[g]));
   unsigned done2 = 0;
-  for (int s = 0; s < steps; ++s) {
-    const ksg_f4 ry = pyz[s * W];
-    float dz[U], dyz[U];
-    if constexpr (M > 0) {
-      const ksg_f4 r0 = pyz[s * W + 1];
-      dz[0] = fabsf(r0.x - qz[0]);
-      dz[1] = fabsf(r0.y - qz[0]);
-      dz[2] = fabsf(r0.z - qz[0]);
-      dz[3] = fabsf(r0.w - qz[0]);
-#pragma unroll
-      for (int a = 1; a < M; ++a) {
-        const ksg_f4 rz = pyz[s * W + 1 + a];
-        dz[0] = fmaxf(dz[0], fabsf(rz.x - qz[a]));
-        dz[1] = fmaxf(dz[1], fabsf(rz.y - qz[a]));
-        dz[2] = fmaxf(dz[2], fabsf(rz.z - qz[a]));
-        dz[3] = fmaxf(dz[3], fabsf(rz.w - qz[a]));
+  {
+    int own = s_lo, r = s_hi + 1, l = s_lo - 1;
+    bool ract = live && r < steps, lact = live && l >= 0;
+    for (;;) {
+      int s, dir;
+      if (own <= s_hi) {
+        s = own++;
+        dir = 0;
+      } else if (ract) {
+        s = r;
+        dir = 1;
+      } else if (lact) {
+        s = l;
+        dir = -1;
+      } else {
+        break;
       }
-      const unsigned zmin = min(min(__float_as_uint(dz[0]), __float_as_uint(dz[1])),
-                                min(__float_as_uint(dz[2]), __float_as_uint(dz[3])));
-      if (__builtin_amdgcn_ballot_w64(zmin < emax) == 0) continue;
-      dyz[0] = fmaxf(fabsf(ry.x - qy), dz[0]);
-      dyz[1] = fmaxf(fabsf(ry.y - qy), dz[1]);
-      dyz[2] = fmaxf(fabsf(ry.z - qy), dz[2]);
-      dyz[3] = fmaxf(fabsf(ry.w - qy), dz[3]);
-    } else {
-      dz[0] = dz[1] = dz[2] = dz[3] = 0.0f;
-      dyz[0] = fabsf(ry.x - qy);
-      dyz[1] = fabsf(ry.y - qy);
-      dyz[2] = fabsf(ry.z - qy);
-      dyz[3] = fabsf(ry.w - qy);
-    }
-    ++done2;
+      const ksg_f4 ry = pyz[s * W];
+      float dz[U], dyz[U];
+      unsigned zmin = 0;
+      if constexpr (M > 0) {
+        const ksg_f4 r0 = pyz[s * W + 1];
+        if (dir != 0) {
+          const float gap = dir > 0 ? r0.x - qkey : qkey - r0.w;
+          if (__builtin_amdgcn_ballot_w64(__float_as_uint(gap) < emax) == 0) {
+            if (dir > 0) ract = false;
+            else lact = false;
+            continue;
+          }
+          if (dir > 0) ract = ++r < steps;
+          else lact = --l >= 0;
+        }
+        shared += 2 * M + 2;
+        dz[0] = fabsf(r0.x - qz[0]);
+        dz[1] = fabsf(r0.y - qz[0]);
+        dz[2] = fabsf(r0.z - qz[0]);
+        dz[3] = fabsf(r0.w - qz[0]);
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      const ksg_f4 rx = px[s * G + g];
-      const float t[U] = {fabsf(rx.x - qx[g]), fabsf(rx.y - qx[g]), fabsf(rx.z - qx[g]),
-                          fabsf(rx.w - qx[g])};
+        for (int a = 1; a < M; ++a) {
+          const ksg_f4 rz = pyz[s * W + 1 + a];
+          dz[0] = fmaxf(dz[0], fabsf(rz.x - qz[a]));
+          dz[1] = fmaxf(dz[1], fabsf(rz.y - qz[a]));
+          dz[2] = fmaxf(dz[2], fabsf(rz.z - qz[a]));
+          dz[3] = fmaxf(dz[3], fabsf(rz.w - qz[a]));
+        }
+        zmin = min(min(__float_as_uint(dz[0]), __float_as_uint(dz[1])),
+                   min(__float_as_uint(dz[2]), __float_as_uint(dz[3])));
+        if (__builtin_amdgcn_ballot_w64(zmin < emax) == 0) continue;
+        dyz[0] = fmaxf(fabsf(ry.x - qy), dz[0]);
+        dyz[1] = fmaxf(fabsf(ry.y - qy), dz[1]);
+        dyz[2] = fmaxf(fabsf(ry.z - qy), dz[2]);
+        dyz[3] = fmaxf(fabsf(ry.w - qy), dz[3]);
+      } else {
+        if (dir > 0) ract = ++r < steps;
+        else if (dir < 0) lact = --l >= 0;
+        shared += 1;
+        dz[0] = dz[1] = dz[2] = dz[3] = 0.0f;
+        dyz[0] = fabsf(ry.x - qy);
+        dyz[1] = fabsf(ry.y - qy);
+        dyz[2] = fabsf(ry.z - qy);
+        dyz[3] = fabsf(ry.w - qy);
+      }
+      // the whole X block of the step is requested at once (one wait, not one per problem)
+      ksg_f4 rx[G];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const float dxz = M > 0 ? fmaxf(t[u], dz[u]) : t[u];
-        cxz[g] += (unsigned)(dxz < eps[g]);
-        cyz[g] += (unsigned)(dyz[u] < eps[g]);
-        if constexpr (M > 0) cz[g] += (unsigned)(dz[u] < eps[g]);
+      for (int g = 0; g < G; ++g) rx[g] = px[s * G + g];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if constexpr (M > 0) {
+          if (__builtin_amdgcn_ballot_w64(zmin < __float_as_uint(eps[g])) == 0) continue;
+        }
+        done2 += g < ng ? 1u : 0u;
+        const float t[U] = {fabsf(rx[g].x - qx[g]), fabsf(rx[g].y - qx[g]), fabsf(rx[g].z - qx[g]),
+                            fabsf(rx[g].w - qx[g])};
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const float dxz = M > 0 ? fmaxf(t[u], dz[u]) : t[u];
+          cxz[g] += (unsigned)(dxz < eps[g]);
+          cyz[g] += (unsigned)(dyz[u] < eps[g]);
+          if constexpr (M > 0) cz[g] += (unsigned)(dz[u] < eps[g]);
+        }
       }
     }
   }
 
   // ---- epilogue: self correction, digamma terms, one partial per (problem, tile) ----
-  const int wave = threadIdx.x >> 6;
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     const int self = eps[g] > 0.0f ? 1 : 0;
@@ -183,9 +273,11 @@ __device__ __forceinline__ void group_tile(const float* __restrict__ base,
     if ((threadIdx.x & 63) == 0) s_red[wave][g] = t;
   }
   if (work && (threadIdx.x & 63) == 0) {
-    // per-problem work units executed by this wave: (steps run) x (problems in the group)
-    atomicAdd(&work[0], (unsigned long long)done1 * (unsigned)ng);
-    atomicAdd(&work[1], (unsigned long long)done2 * (unsigned)ng);
+    // work executed by this wave, in units of 4 references x 64 lanes: problem-steps of
+    // pass 1 and pass 2, and shared-part operations
+    atomicAdd(&work[0], (unsigned long long)done1);
+    atomicAdd(&work[1], (unsigned long long)done2);
+    atomicAdd(&work[2], (unsigned long long)shared);
   }
   __syncthreads();
   if ((int)threadIdx.x < ng)

@@ -104,8 +104,61 @@ hipError_t launch_perm_check(const int32_t* perms, int n_perm, int n, int* d_fla
   return hipGetLastError();
 }
 
-// Interleaved group blocks from packed columns (layouts in internal.h).  grid.x: chunks of
-// 64 four-row steps, grid.y: groups (strided).
+// Key order of a Y/Z set: the rank of row i among the n keys (column Z_1, or Y when m = 0)
+// under the total order of the FP32 values' ordered bit patterns, ties by row index, so that
+// the ranks are a permutation of [0, n) whatever the data; sigma[rank] = i, and the padding
+// rows n..n_pad-1 map to themselves.  O(n^2) comparisons against LDS tiles of the keys: a
+// few microseconds at n = 10^4, negligible beside the search.  grid.x: chunks of 256 rows,
+// grid.y: groups (strided); only the group that writes the Y/Z block sorts.
+__device__ __forceinline__ unsigned ordered_bits(float v) {
+  const unsigned b = __float_as_uint(v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__global__ __launch_bounds__(256) void key_order_kernel(const GroupDesc* __restrict__ descs,
+                                                        int n_groups, float* __restrict__ base) {
+  constexpr int kChunk = 2048;
+  __shared__ unsigned s_key[kChunk];
+  for (int gi = blockIdx.y; gi < n_groups; gi += gridDim.y) {
+    const GroupDesc& gd = descs[gi];
+    const int n = gd.n;
+    const int i0 = blockIdx.x * 256;
+    if (!gd.write_yz || i0 >= gd.n_pad) continue;  // uniform over the block
+    const float* key = base + (gd.m > 0 ? gd.z_off[0] : gd.y_off);
+    int32_t* sigma = reinterpret_cast<int32_t*>(base + gd.sigma_off);
+    const int i = i0 + (int)threadIdx.x;
+    if (i0 >= n) {
+      if (i < gd.n_pad) sigma[i] = i;
+      continue;
+    }
+    const unsigned long long ki =
+        i < n ? ((unsigned long long)ordered_bits(key[i]) << 32) | (unsigned)i : ~0ull;
+    int rank = 0;
+    for (int j0 = 0; j0 < n; j0 += kChunk) {
+      const int cnt = min(kChunk, n - j0);
+      __syncthreads();
+      for (int t = threadIdx.x; t < cnt; t += 256) s_key[t] = ordered_bits(key[j0 + t]);
+      __syncthreads();
+      for (int t = 0; t < cnt; ++t) {
+        const unsigned long long kj = ((unsigned long long)s_key[t] << 32) | (unsigned)(j0 + t);
+        rank += kj < ki ? 1 : 0;
+      }
+    }
+    if (i < n) sigma[rank] = i;
+    else if (i < gd.n_pad) sigma[i] = i;
+  }
+}
+
+hipError_t launch_key_order(const GroupDesc* d_gdesc, int n_groups, int max_pad, float* base,
+                            hipStream_t stream) {
+  if (n_groups <= 0) return hipSuccess;
+  dim3 grid((max_pad + 255) / 256, n_groups < 65535 ? n_groups : 65535);
+  hipLaunchKernelGGL(key_order_kernel, grid, dim3(256), 0, stream, d_gdesc, n_groups, base);
+  return hipGetLastError();
+}
+
+// Interleaved group blocks from packed columns (layouts in internal.h), rows in key order.
+// grid.x: chunks of 64 four-row steps, grid.y: groups (strided).
 __global__ __launch_bounds__(256) void interleave_kernel(const GroupDesc* __restrict__ descs,
                                                          int n_groups, float* __restrict__ base) {
   for (int gi = blockIdx.y; gi < n_groups; gi += gridDim.y) {
@@ -115,10 +168,15 @@ __global__ __launch_bounds__(256) void interleave_kernel(const GroupDesc* __rest
     if (s0 >= steps) continue;
     const int s1 = min(steps, s0 + 64);
     const int G = gd.G;
+    const int32_t* sigma = reinterpret_cast<const int32_t*>(base + gd.sigma_off);
+    auto src_row = [&](int row) {
+      const unsigned r = (unsigned)sigma[row];
+      return r < (unsigned)gd.n_pad ? (int)r : row;  // sigma is a permutation; never trust it blindly
+    };
     float* xi = base + gd.xi_off;
     for (int e = s0 * G * 4 + threadIdx.x; e < s1 * G * 4; e += 256) {
       const int s = e / (G * 4), r = e - s * G * 4, g = r >> 2, u = r & 3;
-      xi[e] = base[gd.x_off[g] + s * 4 + u];
+      xi[e] = base[gd.x_off[g] + src_row(s * 4 + u)];
     }
     if (gd.write_yz) {
       const int W = gd.m + 1;
@@ -126,7 +184,7 @@ __global__ __launch_bounds__(256) void interleave_kernel(const GroupDesc* __rest
       for (int e = s0 * W * 4 + threadIdx.x; e < s1 * W * 4; e += 256) {
         const int s = e / (W * 4), r = e - s * W * 4, a = r >> 2, u = r & 3;
         const uint32_t src = a == 0 ? gd.y_off : gd.z_off[a - 1];
-        yzi[e] = base[src + s * 4 + u];
+        yzi[e] = base[src + src_row(s * 4 + u)];
       }
     }
   }

@@ -76,7 +76,6 @@ struct ksg_ctx {
     return t ? t : 8;
   }
   static double algorithmic_ops(const ksg::Problem& p, int ng);
-  static double group_shared_ops(const ksg::Problem& p);
   unsigned long long* d_work = nullptr;  // grouped-kernel work counters (timing mode)
 
   // KSG_OPT_TIMING: events around each search launch, harvested by ksg_take_timing.
