@@ -114,7 +114,8 @@ int ksg_autotune(ksg_ctx* ctx, int64_t n, const char* cache_path, int32_t* tuned
  * memory traffic: kind 0 v_sub_f32, 1 v_max3_f32 (|.| operands), 2 v_cmp_lt_f32 + v_addc
  * (a compare-and-count, two instructions), 3 v_med3_f32, 4 v_fma_f32, 5 v_max_f32, 6
  * v_max_f32 with |.| (VOP3), 7 v_min_u32, 8 v_cndmask_b32, 9 v_add_u32, 10 v_cmp_lt_f32 into an
- * SGPR pair, 11 v_and_b32, 12 v_sub_f32 with an SGPR operand, 13 v_min3_f32.  Synchronises.
+ * SGPR pair, 11 v_and_b32, 12 v_sub_f32 with an SGPR operand, 13 v_min3_f32, 14 v_sub_u32,
+ * 15 v_lshrrev_b32, 16 v_add3_u32, 17 v_mov_b32 from an SGPR.  Synchronises.
  * Errors: KSG_EINVAL, KSG_EDEVICE. */
 int ksg_valu_probe(ksg_ctx* ctx, int32_t kind, int32_t iters, double* lane_ops_per_s);
 
@@ -123,11 +124,17 @@ int ksg_valu_probe(ksg_ctx* ctx, int32_t kind, int32_t iters, double* lane_ops_p
  * milliseconds, with their launch count and algorithmic FP32 operation count.  Problems
  * searched alone count N(N-1)(4D+2) (per ordered pair D subtractions, D-1 maxima and 1
  * compare for the radius, the same plus 3 compares for the counts).  A group of problems that
- * share Y and Z counts the shared Y/Z work once per pair (2m+2 per pass, skip test included;
- * 1 for the count pass when m = 0) plus, per problem, 3 (radius) and 5 (counts) operations on
- * every pair of the reference steps the kernel did not skip (counted on the device).
+ * share Y and Z counts, on the reference steps the kernel executed (its key windows and
+ * skips decide which; counted on the device in units of 4 references x 64 lanes), the shared
+ * Y/Z work once per pair (2m+2 per pass, skip test included; 1 for the count pass when m = 0)
+ * plus, per problem, 3 (radius) and 5 (counts) operations for every problem the step ran.
  * Synchronises the stream; resets the accumulators.  Outputs are host pointers. */
 int ksg_take_timing(ksg_ctx* ctx, double* ms, int64_t* launches, double* ops);
+
+/* The grouped kernel's device work counters behind the last ksg_take_timing (host uint64[3]):
+ * problem-steps of the radius pass, problem-steps of the count pass, and shared-part
+ * operations / 256, each step being 4 references x 64 query lanes.  Errors: KSG_EINVAL. */
+int ksg_last_work(ksg_ctx* ctx, uint64_t* counters);
 
 /* ---------------------------------------------------------------------------
  * Single estimate (direct estimator access, Summary estimator paragraph).

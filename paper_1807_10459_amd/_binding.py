@@ -77,6 +77,7 @@ def _load():
         "ksg_ctx_set_option": ([vp, i32, i64], i32),
         "ksg_autotune": ([vp, i64, C.c_char_p, vp], i32),
         "ksg_valu_probe": ([vp, i32, i32, C.POINTER(d)], i32),
+        "ksg_last_work": ([vp, vp], i32),
         "ksg_take_timing": ([vp, C.POINTER(d), C.POINTER(i64), C.POINTER(d)], i32),
         "cmi_ksg": ([vp, vp, vp, vp, i64, vp, i32, C.POINTER(d)], i32),
         "cmi_ksg_batch": ([vp, C.POINTER(_Problem), i32, vp], i32),
@@ -232,6 +233,13 @@ class Context:
         ms, n, ops = C.c_double(), C.c_int64(), C.c_double()
         self._check(lib.ksg_take_timing(self._h, C.byref(ms), C.byref(n), C.byref(ops)), "ksg_take_timing")
         return ms.value, n.value, ops.value
+
+    def last_work(self):
+        """Grouped-kernel work counters behind the last take_timing: (radius-pass problem-steps,
+        count-pass problem-steps, shared operations / 256); a step is 4 references x 64 lanes."""
+        w = (C.c_uint64 * 3)()
+        self._check(lib.ksg_last_work(self._h, w), "ksg_last_work")
+        return tuple(int(v) for v in w)
 
     # ---------------------------------------------------------------- estimator
     def cmi(self, x, y, z=None, k: int = 4) -> float:

@@ -796,10 +796,18 @@ extern "C" int ksg_take_timing(ksg_ctx* c, double* ms, int64_t* launches, double
     KSG_HIP(c, hipMemcpy(w, c->d_work, sizeof w, hipMemcpyDeviceToHost));
     KSG_HIP(c, hipMemset(c->d_work, 0, sizeof w));
   }
+  for (int i = 0; i < 3; ++i) c->last_work[i] = w[i];
   *ms = total;
   *launches = (int64_t)c->timed.size();
   *ops = c->timed_ops + 256.0 * (3.0 * (double)w[0] + 5.0 * (double)w[1] + (double)w[2]);
   c->timed.clear();
   c->timed_ops = 0.0;
+  return KSG_OK;
+}
+
+extern "C" int ksg_last_work(ksg_ctx* c, uint64_t* counters) {
+  if (!c) return KSG_EINVAL;
+  if (!counters) return c->fail(KSG_EINVAL, "ksg_last_work: null output");
+  for (int i = 0; i < 3; ++i) counters[i] = (uint64_t)c->last_work[i];
   return KSG_OK;
 }

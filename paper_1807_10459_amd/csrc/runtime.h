@@ -83,6 +83,7 @@ struct ksg_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
   std::vector<hipEvent_t> event_pool;
   double timed_ops = 0.0;
+  unsigned long long last_work[3] = {0, 0, 0};  // counters read by the last take_timing
   hipEvent_t get_event();
 
   int fail(int status, const char* fmt, ...);

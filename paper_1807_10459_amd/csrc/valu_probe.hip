@@ -49,8 +49,16 @@ __global__ __launch_bounds__(256) void valu_probe_kernel(int iters, float seed, 
         asm volatile("v_and_b32 %0, %0, %1" : "+v"(c[i]) : "v"(c[0]));
       } else if constexpr (KIND == 12) {  // FP32 subtract with an SGPR operand (VOP2)
         asm volatile("v_sub_f32 %0, %1, %0" : "+v"(a[i]) : "s"(seed));
-      } else {  // FP32 min3 (VOP3)
+      } else if constexpr (KIND == 13) {  // FP32 min3 (VOP3)
         asm volatile("v_min3_f32 %0, %0, %1, %0" : "+v"(a[i]) : "v"(s));
+      } else if constexpr (KIND == 14) {  // u32 subtract (VOP2)
+        asm volatile("v_sub_u32 %0, %0, %1" : "+v"(c[i]) : "v"(c[0]));
+      } else if constexpr (KIND == 15) {  // logical shift right (VOP2)
+        asm volatile("v_lshrrev_b32 %0, 1, %0" : "+v"(c[i]));
+      } else if constexpr (KIND == 16) {  // u32 add of three operands (VOP3)
+        asm volatile("v_add3_u32 %0, %0, %1, %0" : "+v"(c[i]) : "v"(c[0]));
+      } else {  // move from an SGPR (VOP1)
+        asm volatile("v_mov_b32 %0, %1" : "=v"(a[i]) : "s"(seed + (float)i));
       }
     }
   }
@@ -66,15 +74,17 @@ using namespace ksg;
 
 extern "C" int ksg_valu_probe(ksg_ctx* c, int32_t kind, int32_t iters, double* lane_ops_per_s) {
   if (!c) return KSG_EINVAL;
-  if (!lane_ops_per_s || kind < 0 || kind > 13 || iters < 1) return c->fail(KSG_EINVAL, "ksg_valu_probe: bad argument");
+  if (!lane_ops_per_s || kind < 0 || kind > 17 || iters < 1) return c->fail(KSG_EINVAL, "ksg_valu_probe: bad argument");
   if (hipSetDevice(c->device) != hipSuccess) return c->fail(KSG_EDEVICE, "hipSetDevice");
-  const void* fns[14] = {(const void*)&valu_probe_kernel<0>,  (const void*)&valu_probe_kernel<1>,
+  const void* fns[18] = {(const void*)&valu_probe_kernel<0>,  (const void*)&valu_probe_kernel<1>,
                          (const void*)&valu_probe_kernel<2>,  (const void*)&valu_probe_kernel<3>,
                          (const void*)&valu_probe_kernel<4>,  (const void*)&valu_probe_kernel<5>,
                          (const void*)&valu_probe_kernel<6>,  (const void*)&valu_probe_kernel<7>,
                          (const void*)&valu_probe_kernel<8>,  (const void*)&valu_probe_kernel<9>,
                          (const void*)&valu_probe_kernel<10>, (const void*)&valu_probe_kernel<11>,
-                         (const void*)&valu_probe_kernel<12>, (const void*)&valu_probe_kernel<13>};
+                         (const void*)&valu_probe_kernel<12>, (const void*)&valu_probe_kernel<13>,
+                         (const void*)&valu_probe_kernel<14>, (const void*)&valu_probe_kernel<15>,
+                         (const void*)&valu_probe_kernel<16>, (const void*)&valu_probe_kernel<17>};
   const int blocks = c->cus * 16;
   int st = c->reserve(c->tmp, 256 * sizeof(float), "probe output");
   if (st) return st;

@@ -349,3 +349,13 @@ def test_autotune_table_and_cache(lib, ctx, tmp_path):
     b = ctx.autotune(2048, cache_path=path)  # served from the cache
     assert a == b
     assert open(path).read().count("\n") == 1
+
+
+def test_valu_probe_classes(lib, ctx):
+    """Every instruction class of the roofline calibration runs and reports a rate below the
+    part's 2 x 16-lane issue ceiling (256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T)."""
+    for kind in range(18):
+        r = ctx.valu_probe(kind, iters=256)
+        assert 1e12 < r < 1.05 * 78.65e12, (kind, r)
+    with pytest.raises(lib.KsgError):
+        ctx.valu_probe(18)
