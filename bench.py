@@ -258,7 +258,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the path shards by targets or work items with no collectives; see DESIGN.md)",
+              "(the path shards by targets or work items with no collectives)",
               file=sys.stderr)
         sys.exit(2)
 
