@@ -9,12 +9,14 @@ batched launch over all (25 - m) x 201 CMI problems (surrogate gathers, k-NN rad
 strict range counts, FP64 digamma sums) and the max-statistic test.  That is 32,964 CMI
 estimates per step.  Inputs are resident in HBM before timing starts.
 
-Prints one JSON line.  The roofline object is for the search kernel: algorithmic FP32
-operations N(N-1)(4D+2) per CMI over its HIP-event time, against the FP32 VALU peak for
-operations that are not fused multiply-adds: the 157.3 TFLOP/s FP32 vector figure counts an
-FMA as two operations, so 78.6 T FP32 lane-operations per second (256 CUs x 4 SIMDs x 32
-FP32 lanes per clock x 2.4 GHz).  cpu_baseline times the CPU oracle on a sample of the same
-CMIs.
+Prints one JSON line.  The roofline object is for the dominant search kernel (the one with
+the most device time in the timed steps; each launch is timed by its own HIP events):
+algorithmic operations executed (as counted by the library: distances, maxima and compares
+of the pairs it visits) over its time, against the FP32 VALU peak for operations that are
+not fused multiply-adds: the 157.3 TFLOP/s FP32 vector figure counts an FMA as two
+operations, so 78.6 T lane-operations per second (256 CUs x 4 SIMDs x 32 lanes per clock x
+2.4 GHz).  "kernels" lists every search kernel the same way.  cpu_baseline times the CPU
+oracle on a sample of the same CMIs.
 """
 from __future__ import annotations
 
@@ -221,18 +223,30 @@ def c4_evaluate(ctx, args, log):
     }
 
 
-def _traffic_record():
-    """HBM bytes per grouped-search launch from the committed counter record, or None when the
-    kernel sources changed since the counters were taken."""
+TRAFFIC_SOURCES = ("ksg_group.inc.h", "ksg_search.inc.h", "ksg_yzcount.hip")
+KERNEL_NAMES = {"radius": "ksg_group_radius_kernel (k-NN radius of each problem of a group, "
+                          "Y/Z distances shared, key-ordered windows)",
+                "yz_count": "ksg_yzcount_kernel (n_YZ and n_Z of every problem of a step at once: "
+                            "rank histogram over the sorted radii)",
+                "x_count": "ksg_group_xcount_kernel (n_XZ of each problem of a group, digamma partial sums)",
+                "single": "ksg_batch_kernel (brute-force radius, counts and digamma partial sums)"}
+
+
+def _kernel_source_hash():
     import hashlib
-    path = os.path.join(ROOT, "profiles", "ksg_group_kernel_traffic.json")
+    return hashlib.sha256(b"".join(open(os.path.join(ROOT, "paper_1807_10459_amd", "csrc", f), "rb").read()
+                                   for f in TRAFFIC_SOURCES)).hexdigest()
+
+
+def _traffic_record(kernel):
+    """HBM bytes per launch of a kernel from the committed counter record, or None when the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "ksg_group_kernels_traffic.json")
     try:
         rec = json.load(open(path))
-        src = b"".join(open(os.path.join(ROOT, "paper_1807_10459_amd", "csrc", f), "rb").read()
-                       for f in ("ksg_group.inc.h", "ksg_search.inc.h"))
-        if hashlib.sha256(src).hexdigest() == rec["kernel_source_sha256"]:
-            return rec["traffic_bytes_per_launch"]
-    except (OSError, KeyError, ValueError):
+        if _kernel_source_hash() == rec["kernel_source_sha256"]:
+            return rec["traffic_bytes_per_launch"].get(kernel)
+    except (OSError, KeyError, ValueError, AttributeError):
         pass
     return None
 
@@ -325,26 +339,35 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     k_ms, k_launches, k_ops = ctx.take_timing()
+    kern = ctx.last_kernels()
     ctx.set_option(ctx.OPT_TIMING, 0)
 
     n_cmi = sum((25 - m) * (N_PERM + 1) for m in FORCED_M)
     ms_step = 1000.0 * wall / args.steps
     value = n_cmi * args.steps / wall
-    achieved = k_ops / (k_ms * 1e-3)  # ops per second of search-kernel time
+    kernels = {}
+    for name, (ms, ops, nl) in kern.items():
+        if nl:
+            kernels[name] = {"ms_per_launch": round(ms / nl, 3), "launches": nl,
+                             "ops_per_launch": ops / nl, "achieved": round(ops / (ms * 1e-3) / 1e12, 3),
+                             "frac": round(ops / (ms * 1e-3) / PEAK_VALU, 4)}
+    dom = max(kernels, key=lambda kname: kern[kname][0])
+    d_ms, d_ops, d_n = kern[dom]
+    achieved = d_ops / (d_ms * 1e-3)
     roofline = {
         "bound": "alu",
         "achieved": round(achieved / 1e12, 3),
         "peak": round(PEAK_VALU / 1e12, 3),
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_VALU, 4),
-        "traffic": _traffic_record() if args.group_size != 0 else None,
-        "kernel": "ksg_group_kernel (k-NN radius + strict counts + digamma partial sums, "
-                  "Y/Z distances shared by each group of candidates/surrogates)" if args.group_size != 0
-                  else "ksg_batch_kernel (k-NN radius + strict counts + digamma partial sums)",
-        "kernel_ms_per_launch": round(k_ms / max(k_launches, 1), 3),
-        "launches": k_launches,
-        "ops_per_launch": k_ops / max(k_launches, 1),
+        "traffic": _traffic_record(dom),
+        "kernel": KERNEL_NAMES[dom],
+        "kernel_ms_per_launch": round(d_ms / d_n, 3),
+        "launches": d_n,
+        "ops_per_launch": d_ops / d_n,
     }
+    search = {"ms_per_step": round(k_ms / args.steps, 3), "kernels": kernels,
+              "achieved_all_kernels": round(k_ops / (k_ms * 1e-3) / 1e12, 3)}
 
     line = {
         "metric": "CMI estimates/sec incl. surrogates (N=10k, k=4)",
@@ -364,6 +387,7 @@ def main():
                                f"{n_cmi} CMIs per step",
                    "n_cmi_per_step": n_cmi},
         "roofline": roofline,
+        "search": search,
         "autotune": {"group_size_k4_by_m": tuned["k<=4"] if tuned else None,
                      "seconds": round(t_tune, 3)},
     }

@@ -119,22 +119,31 @@ int ksg_autotune(ksg_ctx* ctx, int64_t n, const char* cache_path, int32_t* tuned
  * Errors: KSG_EINVAL, KSG_EDEVICE. */
 int ksg_valu_probe(ksg_ctx* ctx, int32_t kind, int32_t iters, double* lane_ops_per_s);
 
-/* With KSG_OPT_TIMING on: device time of the search kernels (search + count + per-tile
- * digamma sums, finalisation excluded) summed over all launches since the last call, in
- * milliseconds, with their launch count and algorithmic FP32 operation count.  Problems
- * searched alone count N(N-1)(4D+2) (per ordered pair D subtractions, D-1 maxima and 1
- * compare for the radius, the same plus 3 compares for the counts).  A group of problems that
- * share Y and Z counts, on the reference steps the kernel executed (its key windows and
- * skips decide which; counted on the device in units of 4 references x 64 lanes), the shared
- * Y/Z work once per pair (2m+2 per pass, skip test included; 1 for the count pass when m = 0)
- * plus, per problem, 3 (radius) and 5 (counts) operations for every problem the step ran.
+/* With KSG_OPT_TIMING on: device time of the search kernels (radius, counts and per-tile
+ * digamma sums, finalisation excluded) summed over all search phases since the last call, in
+ * milliseconds, with their count and algorithmic operation count.  Problems searched alone
+ * count N(N-1)(4D+2) (per ordered pair D subtractions, D-1 maxima and 1 compare for the
+ * radius, the same plus 3 compares for the counts).  Problems searched in groups that share
+ * Y and Z are counted on the device over the work executed (key windows and exact skips
+ * decide which reference steps run): the shared Y/Z distances once per pair of an executed
+ * step (2m+2 for the radius, 2m for the X counts), 3 operations per pair for each problem's
+ * radius and X count steps, and for the Y/Z counts, per visited reference, its d^Z and d^YZ
+ * (2m+1) plus one compare per binary-search level for each of the two ranks.
  * Synchronises the stream; resets the accumulators.  Outputs are host pointers. */
 int ksg_take_timing(ksg_ctx* ctx, double* ms, int64_t* launches, double* ops);
 
-/* The grouped kernel's device work counters behind the last ksg_take_timing (host uint64[3]):
- * problem-steps of the radius pass, problem-steps of the count pass, and shared-part
- * operations / 256, each step being 4 references x 64 query lanes.  Errors: KSG_EINVAL. */
+/* The grouped kernels' device work counters behind the last ksg_take_timing (host
+ * uint64[5]): problem-steps of the radius kernel, problem-steps of the X count kernel, the
+ * radius kernel's shared-part operations / 256 (a step is 4 references x 64 query lanes), the
+ * Y/Z count kernel's operations, the X count kernel's shared-part operations / 256.
+ * Errors: KSG_EINVAL. */
 int ksg_last_work(ksg_ctx* ctx, uint64_t* counters);
+
+/* Per-kernel split of the last ksg_take_timing (host arrays of 4, in the order: grouped
+ * radius kernel, Y/Z count kernel, X count kernel, single-problem search kernel): device
+ * milliseconds (each launch timed by its own pair of events), algorithmic operations (as
+ * counted for ksg_take_timing) and launch counts.  Errors: KSG_EINVAL. */
+int ksg_last_kernels(ksg_ctx* ctx, double* ms, double* ops, int64_t* launches);
 
 /* ---------------------------------------------------------------------------
  * Single estimate (direct estimator access, Summary estimator paragraph).

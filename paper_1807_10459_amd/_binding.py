@@ -78,6 +78,7 @@ def _load():
         "ksg_autotune": ([vp, i64, C.c_char_p, vp], i32),
         "ksg_valu_probe": ([vp, i32, i32, C.POINTER(d)], i32),
         "ksg_last_work": ([vp, vp], i32),
+        "ksg_last_kernels": ([vp, vp, vp, vp], i32),
         "ksg_take_timing": ([vp, C.POINTER(d), C.POINTER(i64), C.POINTER(d)], i32),
         "cmi_ksg": ([vp, vp, vp, vp, i64, vp, i32, C.POINTER(d)], i32),
         "cmi_ksg_batch": ([vp, C.POINTER(_Problem), i32, vp], i32),
@@ -235,11 +236,20 @@ class Context:
         return ms.value, n.value, ops.value
 
     def last_work(self):
-        """Grouped-kernel work counters behind the last take_timing: (radius-pass problem-steps,
-        count-pass problem-steps, shared operations / 256); a step is 4 references x 64 lanes."""
-        w = (C.c_uint64 * 3)()
+        """Grouped-kernel work counters behind the last take_timing: (radius problem-steps,
+        X-count problem-steps, radius shared operations / 256, Y/Z count operations, X-count
+        shared operations / 256); a step is 4 references x 64 lanes."""
+        w = (C.c_uint64 * 5)()
         self._check(lib.ksg_last_work(self._h, w), "ksg_last_work")
         return tuple(int(v) for v in w)
+
+    KERNELS = ("radius", "yz_count", "x_count", "single")
+
+    def last_kernels(self):
+        """Per-kernel {name: (ms, ops, launches)} of the last take_timing."""
+        ms, ops, n = (C.c_double * 4)(), (C.c_double * 4)(), (C.c_int64 * 4)()
+        self._check(lib.ksg_last_kernels(self._h, ms, ops, n), "ksg_last_kernels")
+        return {k: (ms[i], ops[i], int(n[i])) for i, k in enumerate(self.KERNELS)}
 
     # ---------------------------------------------------------------- estimator
     def cmi(self, x, y, z=None, k: int = 4) -> float:

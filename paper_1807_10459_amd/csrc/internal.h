@@ -55,9 +55,22 @@ struct alignas(16) GroupDesc {
   int32_t part_base;
   int32_t write_yz;
   uint32_t sigma_off;
-  int32_t pad_;
+  uint32_t e_off;  // element offset of the group's radii E[row][G] and terms T[row][G]
 };
 static_assert(sizeof(GroupDesc) % 16 == 0, "GroupDesc is copied as an array of 16-byte aligned records");
+
+// Y/Z count work (ksg_yzcount.hip): the problems of one Y/Z set held by a run of consecutive
+// groups of one launch, slots [slot0, slot0 + n_slots) of the run (slot = group-in-run * G +
+// g, all real problems).  Slot s of the run has its radius and term at element
+//   e_off + (s / G) * n_pad * G + row * G + s % G   of E (FP32) and T (FP64).
+constexpr int kYZSlots = 2048;
+struct YZDesc {
+  uint32_t yzi_off;  // key-ordered YZ block of the set
+  uint32_t e_off;    // element offset of the run's first group
+  int32_t n, n_pad, G;
+  int32_t slot0, n_slots;
+  int32_t pad_;
+};
 
 // Work item: one query tile of one problem (or group); prob < 0 marks an empty slot.
 struct WorkItem {
@@ -108,9 +121,16 @@ struct MaxStatOut {
 hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                              const double* d_htab, double* d_partials, int shape, int kp,
                              hipStream_t stream);
-hipError_t launch_ksg_group(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
-                            int n_items, const double* d_htab, double* d_partials, int m, int G,
-                            int kp, unsigned long long* d_work, hipStream_t stream);
+hipError_t launch_ksg_group_radius(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
+                                   int n_items, float* E, int m, int G, int kp,
+                                   unsigned long long* d_work, hipStream_t stream);
+hipError_t launch_ksg_yzcount(const float* base, const YZDesc* d_ydesc, const WorkItem* d_items,
+                              int n_items, const float* E, double* T, const double* d_htab, int m,
+                              unsigned long long* d_work, hipStream_t stream);
+hipError_t launch_ksg_group_xcount(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
+                                   int n_items, const float* E, const double* T, const double* d_htab,
+                                   double* d_partials, int m, int G, unsigned long long* d_work,
+                                   hipStream_t stream);
 hipError_t launch_key_order(const GroupDesc* d_gdesc, int n_groups, int max_pad, float* base,
                             hipStream_t stream);
 hipError_t launch_interleave(const GroupDesc* d_gdesc, int n_groups, int max_pad, float* base,

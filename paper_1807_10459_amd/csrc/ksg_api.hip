@@ -194,7 +194,7 @@ extern "C" void ksg_ctx_destroy(ksg_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->htab, &c->pool, &c->desc, &c->items, &c->partials, &c->jobs, &c->tmp,
+  for (DevBuf* b : {&c->htab, &c->pool, &c->desc, &c->items, &c->partials, &c->jobs, &c->tmp, &c->ebuf, &c->tbuf,
                     &c->embed, &c->cmi, &c->aux, &c->feat})
     if (b->ptr) (void)hipFree(b->ptr);
   if (c->d_counter) (void)hipFree(c->d_counter);
@@ -204,6 +204,7 @@ extern "C" void ksg_ctx_destroy(ksg_ctx* c) {
   if (c->staging) (void)hipHostFree(c->staging);
   if (c->staging_done) (void)hipEventDestroy(c->staging_done);
   for (auto& pr : c->timed) c->event_pool.insert(c->event_pool.end(), {pr.first, pr.second});
+  for (auto& sp : c->spans) c->event_pool.insert(c->event_pool.end(), {sp.a, sp.b});
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   (void)hipGetLastError();
   delete c;
@@ -224,8 +225,8 @@ extern "C" int ksg_ctx_set_option(ksg_ctx* c, int option, int64_t value) {
     case KSG_OPT_TIMING:
       c->timing = value != 0;
       if (c->timing && !c->d_work) {
-        if (hipMalloc(&c->d_work, 3 * sizeof(unsigned long long)) != hipSuccess ||
-            hipMemset(c->d_work, 0, 3 * sizeof(unsigned long long)) != hipSuccess) {
+        if (hipMalloc(&c->d_work, 5 * sizeof(unsigned long long)) != hipSuccess ||
+            hipMemset(c->d_work, 0, 5 * sizeof(unsigned long long)) != hipSuccess) {
           (void)hipGetLastError();
           c->d_work = nullptr;
           c->timing = false;
@@ -495,9 +496,13 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     if (group_of[order[r]] < 0) units.push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
   std::vector<WorkItem> items = order_items(units);
 
-  // group descriptors and items, one launch per (m, G, KP) class
+  // ---- groups: descriptors, launch chunks, Y/Z count descriptors, work items ----
+  // Groups of one (m, G, KP) class run as chunks of consecutive groups, each chunk three
+  // launches: radius (eps to E), Y/Z counts (terms to T), X counts (partial sums).  A chunk's
+  // E (FP32) and T (FP64) hold G x n_pad elements per group, at most kChunkElems in all.
+  constexpr int64_t kChunkElems = int64_t(1) << 27;
   std::vector<GroupDesc> gdescs(groups.size());
-  std::map<std::array<int, 3>, std::vector<Unit>> classes;
+  std::map<std::array<int, 3>, std::vector<int>> class_groups;  // in creation order
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const Problem& p0 = probs[groups[gi][0]];
     GroupDesc& gd = gdescs[gi];
@@ -522,26 +527,107 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     gd.n_tiles = n_tiles_of(i0);
     gd.part_base = group_part[gi];
     const int gkp = p0.k + 1 <= 5 ? 5 : 9;
-    classes[{p0.dz, group_size_of[gi], gkp}].push_back(
-        Unit{(int)gi, gd.n_tiles, cost(i0) * gd.ng});
+    class_groups[{p0.dz, group_size_of[gi], gkp}].push_back((int)gi);
   }
-  std::vector<std::vector<WorkItem>> group_items;
-  for (auto& kv : classes) {
-    std::stable_sort(kv.second.begin(), kv.second.end(),
-                     [](const Unit& a, const Unit& b) { return a.cost > b.cost; });
-    group_items.push_back(order_items(kv.second));
+  struct Chunk {
+    std::array<int, 3> cls;     // m, G, KP
+    std::vector<WorkItem> items;  // radius and X count launches (same items)
+    size_t item_off = 0;
+    size_t ydesc_off = 0, n_ydesc = 0;
+    size_t yitem_off = 0, n_yitems = 0;
+  };
+  std::vector<Chunk> chunks;
+  std::vector<YZDesc> ydescs;
+  std::vector<WorkItem> yitems;
+  int64_t chunk_elems_max = 0;
+  for (auto& kv : class_groups) {
+    const std::vector<int>& gl = kv.second;
+    size_t a = 0;
+    while (a < gl.size()) {
+      // the chunk: groups gl[a, b)
+      int64_t elems = 0;
+      size_t b = a;
+      while (b < gl.size()) {
+        const int64_t e = (int64_t)gdescs[gl[b]].G * gdescs[gl[b]].n_pad;
+        if (b > a && elems + e > kChunkElems) break;
+        gdescs[gl[b]].e_off = (uint32_t)elems;
+        elems += e;
+        ++b;
+      }
+      chunk_elems_max = std::max(chunk_elems_max, elems);
+      Chunk c;
+      c.cls = kv.first;
+      std::vector<Unit> units;
+      for (size_t q = a; q < b; ++q)
+        units.push_back(Unit{gl[q], gdescs[gl[q]].n_tiles, cost(groups[gl[q]][0]) * gdescs[gl[q]].ng});
+      std::stable_sort(units.begin(), units.end(), [](const Unit& u, const Unit& v) { return u.cost > v.cost; });
+      c.items = order_items(units);
+      // runs of consecutive groups of one Y/Z set -> slot ranges of at most kYZSlots
+      c.ydesc_off = ydescs.size();
+      size_t r0 = a;
+      while (r0 < b) {
+        size_t r1 = r0 + 1;
+        while (r1 < b && gdescs[gl[r1]].yzi_off == gdescs[gl[r0]].yzi_off) ++r1;
+        const GroupDesc& f = gdescs[gl[r0]];
+        int n_valid = 0;  // groups are filled in order, only the last of a set can be short
+        for (size_t q = r0; q < r1; ++q) n_valid = (int)(q - r0) * f.G + gdescs[gl[q]].ng;
+        for (int s0 = 0; s0 < n_valid; s0 += kYZSlots) {
+          YZDesc y;
+          std::memset(&y, 0, sizeof y);
+          y.yzi_off = f.yzi_off;
+          y.e_off = f.e_off;
+          y.n = f.n;
+          y.n_pad = f.n_pad;
+          y.G = f.G;
+          y.slot0 = s0;
+          y.n_slots = std::min(kYZSlots, n_valid - s0);
+          const int di = (int)ydescs.size();
+          ydescs.push_back(y);
+          for (int row = 0; row < f.n; ++row) yitems.push_back(WorkItem{di, row});
+        }
+        r0 = r1;
+      }
+      c.n_ydesc = ydescs.size() - c.ydesc_off;
+      chunks.push_back(std::move(c));
+      a = b;
+    }
+  }
+  if (!groups.empty()) {
+    st = reserve(ebuf, sizeof(float) * chunk_elems_max, "group radii");
+    if (!st) st = reserve(tbuf, sizeof(double) * chunk_elems_max, "group count terms");
+    if (st) return st;
   }
 
   // ---- upload: one pinned staging block, one copy per array ----
   size_t n_gitems = 0;
-  for (auto& v : group_items) n_gitems += v.size();
+  for (Chunk& c : chunks) {
+    c.item_off = items.size() + n_gitems;
+    n_gitems += c.items.size();
+  }
+  {
+    size_t off = items.size() + n_gitems;
+    size_t yoff = 0;
+    for (Chunk& c : chunks) {
+      // Y/Z items of the chunk: those whose descriptor lies in the chunk's range
+      c.yitem_off = off;
+      size_t cnt = 0;
+      while (yoff < yitems.size() && (size_t)yitems[yoff].prob < c.ydesc_off + c.n_ydesc) {
+        ++cnt;
+        ++yoff;
+      }
+      c.n_yitems = cnt;
+      off += cnt;
+    }
+  }
+  const size_t n_all_items = items.size() + n_gitems + yitems.size();
   const size_t sz_desc = sizeof(ProbDesc) * np;
-  const size_t sz_items = sizeof(WorkItem) * (items.size() + n_gitems);
-  const size_t sz_jobs = sizeof(PackJob) * jobs.size();
   const size_t sz_g = sizeof(GroupDesc) * gdescs.size();
-  st = reserve_host(sz_desc + sz_items + sz_jobs + sz_g + 64);
+  const size_t sz_y = sizeof(YZDesc) * ydescs.size();
+  const size_t sz_items = sizeof(WorkItem) * n_all_items;
+  const size_t sz_jobs = sizeof(PackJob) * jobs.size();
+  st = reserve_host(sz_desc + sz_g + sz_y + sz_items + sz_jobs + 64);
   if (st) return st;
-  st = reserve(desc, sz_desc + sz_g, "descriptors");
+  st = reserve(desc, sz_desc + sz_g + sz_y, "descriptors");
   if (!st) st = reserve(this->items, std::max<size_t>(sz_items, 16), "work items");
   if (!st) st = reserve(this->jobs, std::max<size_t>(sz_jobs, 16), "pack jobs");
   if (!st) st = reserve(partials, sizeof(double) * std::max(part, 1), "partial sums");
@@ -549,18 +635,15 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   char* h = static_cast<char*>(staging);
   std::memcpy(h, descs.data(), sz_desc);
   if (sz_g) std::memcpy(h + sz_desc, gdescs.data(), sz_g);
-  char* hi = h + sz_desc + sz_g;
-  if (!items.empty()) std::memcpy(hi, items.data(), sizeof(WorkItem) * items.size());
-  size_t off = items.size();
-  std::vector<size_t> gitem_off;
-  for (auto& v : group_items) {
-    gitem_off.push_back(off);
-    std::memcpy(hi + sizeof(WorkItem) * off, v.data(), sizeof(WorkItem) * v.size());
-    off += v.size();
-  }
+  if (sz_y) std::memcpy(h + sz_desc + sz_g, ydescs.data(), sz_y);
+  char* hi = h + sz_desc + sz_g + sz_y;
+  WorkItem* hw = reinterpret_cast<WorkItem*>(hi);
+  if (!items.empty()) std::memcpy(hw, items.data(), sizeof(WorkItem) * items.size());
+  for (const Chunk& c : chunks) std::memcpy(hw + c.item_off, c.items.data(), sizeof(WorkItem) * c.items.size());
+  if (!yitems.empty()) std::memcpy(hw + items.size() + n_gitems, yitems.data(), sizeof(WorkItem) * yitems.size());
   char* hj = hi + sz_items;
   if (sz_jobs) std::memcpy(hj, jobs.data(), sz_jobs);
-  KSG_HIP(this, hipMemcpyAsync(desc.ptr, h, sz_desc + sz_g, hipMemcpyHostToDevice, stream));
+  KSG_HIP(this, hipMemcpyAsync(desc.ptr, h, sz_desc + sz_g + sz_y, hipMemcpyHostToDevice, stream));
   if (sz_items) KSG_HIP(this, hipMemcpyAsync(this->items.ptr, hi, sz_items, hipMemcpyHostToDevice, stream));
   if (sz_jobs) KSG_HIP(this, hipMemcpyAsync(this->jobs.ptr, hj, sz_jobs, hipMemcpyHostToDevice, stream));
   KSG_HIP(this, hipEventRecord(staging_done, stream));
@@ -584,6 +667,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     if (st) return st;
   }
   const GroupDesc* d_gdesc = (const GroupDesc*)((char*)desc.ptr + sz_desc);
+  const YZDesc* d_ydesc = (const YZDesc*)((char*)desc.ptr + sz_desc + sz_g);
   if (!groups.empty()) {
     KSG_HIP(this, launch_key_order(d_gdesc, (int)groups.size(), max_pad, pool_base, stream));
     KSG_HIP(this, launch_interleave(d_gdesc, (int)groups.size(), max_pad, pool_base, stream));
@@ -596,19 +680,46 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     KSG_HIP(this, hipEventRecord(t0, stream));
   }
   const WorkItem* d_items = (const WorkItem*)this->items.ptr;
-  {
-    size_t ci = 0;
-    for (auto& kv : classes) {
-      KSG_HIP(this, launch_ksg_group(pool_base, d_gdesc, d_items + gitem_off[ci], (int)group_items[ci].size(),
-                                     (const double*)htab.ptr, (double*)partials.ptr, kv.first[0],
-                                     kv.first[1], kv.first[2], timing ? d_work : nullptr, stream));
-      ++ci;
-    }
+  float* d_e = static_cast<float*>(ebuf.ptr);
+  double* d_t = static_cast<double*>(tbuf.ptr);
+  unsigned long long* d_w = timing ? d_work : nullptr;
+  // In timing mode every launch is bracketed by its own pair of events (per-kernel times).
+  hipEvent_t span_a = nullptr;
+  auto span_begin = [&]() -> int {
+    if (!timing) return KSG_OK;
+    span_a = get_event();
+    if (!span_a) return fail(KSG_EDEVICE, "cannot create timing events");
+    KSG_HIP(this, hipEventRecord(span_a, stream));
+    return KSG_OK;
+  };
+  auto span_end = [&](int kind) -> int {
+    if (!timing) return KSG_OK;
+    hipEvent_t b = get_event();
+    if (!b) return fail(KSG_EDEVICE, "cannot create timing events");
+    KSG_HIP(this, hipEventRecord(b, stream));
+    spans.push_back(Span{span_a, b, kind});
+    return KSG_OK;
+  };
+  for (const Chunk& c : chunks) {
+    const int m = c.cls[0], G = c.cls[1], kp_c = c.cls[2];
+    if ((st = span_begin())) return st;
+    KSG_HIP(this, launch_ksg_group_radius(pool_base, d_gdesc, d_items + c.item_off, (int)c.items.size(), d_e,
+                                          m, G, kp_c, d_w, stream));
+    if ((st = span_end(0)) || (st = span_begin())) return st;
+    KSG_HIP(this, launch_ksg_yzcount(pool_base, d_ydesc, d_items + c.yitem_off, (int)c.n_yitems, d_e, d_t,
+                                     (const double*)htab.ptr, m, d_w, stream));
+    if ((st = span_end(1)) || (st = span_begin())) return st;
+    KSG_HIP(this, launch_ksg_group_xcount(pool_base, d_gdesc, d_items + c.item_off, (int)c.items.size(), d_e,
+                                          d_t, (const double*)htab.ptr, (double*)partials.ptr, m, G, d_w,
+                                          stream));
+    if ((st = span_end(2))) return st;
   }
   if (!items.empty()) {
     const int shape = common_shape;
+    if ((st = span_begin())) return st;
     KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items, (int)items.size(),
                                     (const double*)htab.ptr, (double*)partials.ptr, shape, kp, stream));
+    if ((st = span_end(3))) return st;
   }
   if (timing) {
     KSG_HIP(this, hipEventRecord(t1, stream));
@@ -618,7 +729,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   }
   KSG_HIP(this, launch_finalize((const ProbDesc*)desc.ptr, np, (const double*)partials.ptr,
                                 (const double*)htab.ptr, d_out, stream));
-  last_items = (int64_t)(items.size() + n_gitems);
+  last_items = (int64_t)(items.size() + n_gitems + yitems.size());
   last_groups = (int64_t)groups.size();
   return KSG_OK;
 }
@@ -626,12 +737,14 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
 // Algorithmic FP32 operations (the roofline's work count).
 // Ungrouped problem: the brute-force count over ordered pairs, N(N-1)(4D+2) (radius: D sub,
 // D-1 max, 1 compare; counts: D sub, D-1 max, 3 compares).
-// Grouped problems are counted by the kernel itself, over the reference steps it executed
-// (units of 4 references x 64 lanes): the Y/Z part once per pair for the whole group --
-// radius pass d^YZ (2m+1: m+1 sub, m max) and the skip test (1 compare); count pass d^Z and
-// d^YZ (2m+1) and the skip test (1), or 1 when m = 0 -- and the per-problem part, radius 3
-// (sub, max, compare) and counts 5 (sub, max, 3 compares) per pair, for every problem whose
-// step was not skipped.  Steps outside a wave's key window are not executed and not counted.
+// Grouped problems are counted by the kernels themselves, over the work they executed.
+// Radius and X count kernels, in units of 4 references x 64 lanes: the shared part once per
+// pair for the whole group -- radius d^YZ (2m+1: m+1 sub, m max) and the skip test (1); X
+// counts d^Z (2m-1) and the skip test (1), nothing when m = 0 -- and the per-problem part,
+// radius 3 (sub, max, compare) and X counts 3 (sub, max, compare) per pair, for every problem
+// whose step ran.  Y/Z count kernel, in operations: per visited reference d^Z and d^YZ
+// (2m+1, or 1) and one binary-search compare per level per rank (two ranks, one when m = 0).
+// Steps outside a wave's key window are not executed and not counted.
 double ksg_ctx::algorithmic_ops(const Problem& p, int) {
   const double pairs = (double)p.n * (double)(p.n - 1);
   return pairs * (4.0 * (p.dx + p.dy + p.dz) + 2.0);
@@ -791,23 +904,52 @@ extern "C" int ksg_take_timing(ksg_ctx* c, double* ms, int64_t* launches, double
     c->event_pool.push_back(pr.first);
     c->event_pool.push_back(pr.second);
   }
-  unsigned long long w[3] = {0, 0, 0};
+  double kms[4] = {0, 0, 0, 0};
+  int64_t kn[4] = {0, 0, 0, 0};
+  for (auto& sp : c->spans) {
+    float t = 0.0f;
+    KSG_HIP(c, hipEventElapsedTime(&t, sp.a, sp.b));
+    kms[sp.kind] += t;
+    kn[sp.kind] += 1;
+    c->event_pool.push_back(sp.a);
+    c->event_pool.push_back(sp.b);
+  }
+  unsigned long long w[5] = {0, 0, 0, 0, 0};
   if (c->d_work) {
     KSG_HIP(c, hipMemcpy(w, c->d_work, sizeof w, hipMemcpyDeviceToHost));
     KSG_HIP(c, hipMemset(c->d_work, 0, sizeof w));
   }
-  for (int i = 0; i < 3; ++i) c->last_work[i] = w[i];
+  for (int i = 0; i < 5; ++i) c->last_work[i] = w[i];
+  const double kops[4] = {256.0 * (3.0 * (double)w[0] + (double)w[2]), (double)w[3],
+                          256.0 * (3.0 * (double)w[1] + (double)w[4]), c->timed_ops};
+  for (int i = 0; i < 4; ++i) {
+    c->last_kernel_ms[i] = kms[i];
+    c->last_kernel_ops[i] = kops[i];
+    c->last_kernel_launches[i] = kn[i];
+  }
   *ms = total;
   *launches = (int64_t)c->timed.size();
-  *ops = c->timed_ops + 256.0 * (3.0 * (double)w[0] + 5.0 * (double)w[1] + (double)w[2]);
+  *ops = kops[0] + kops[1] + kops[2] + kops[3];
   c->timed.clear();
+  c->spans.clear();
   c->timed_ops = 0.0;
+  return KSG_OK;
+}
+
+extern "C" int ksg_last_kernels(ksg_ctx* c, double* ms, double* ops, int64_t* launches) {
+  if (!c) return KSG_EINVAL;
+  if (!ms || !ops || !launches) return c->fail(KSG_EINVAL, "ksg_last_kernels: null output");
+  for (int i = 0; i < 4; ++i) {
+    ms[i] = c->last_kernel_ms[i];
+    ops[i] = c->last_kernel_ops[i];
+    launches[i] = c->last_kernel_launches[i];
+  }
   return KSG_OK;
 }
 
 extern "C" int ksg_last_work(ksg_ctx* c, uint64_t* counters) {
   if (!c) return KSG_EINVAL;
   if (!counters) return c->fail(KSG_EINVAL, "ksg_last_work: null output");
-  for (int i = 0; i < 3; ++i) counters[i] = (uint64_t)c->last_work[i];
+  for (int i = 0; i < 5; ++i) counters[i] = (uint64_t)c->last_work[i];
   return KSG_OK;
 }

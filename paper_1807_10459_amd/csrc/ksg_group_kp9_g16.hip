@@ -4,9 +4,9 @@
 
 namespace ksg {
 
-#define KSG_G(M) reinterpret_cast<const void*>(&ksg_group_kernel<M, 16, 9>)
-const void* group_kernels_kp9_g16[15] = {KSG_G(0),  KSG_G(1),  KSG_G(2),  KSG_G(3), KSG_G(4),
-                                        KSG_G(5),  KSG_G(6),  KSG_G(7),  KSG_G(8), KSG_G(9),
-                                        KSG_G(10), KSG_G(11), KSG_G(12), KSG_G(13), KSG_G(14)};
+#define KSG_R(M) reinterpret_cast<const void*>(&ksg_group_radius_kernel<M, 16, 9>)
+const void* group_radius_kernels_kp9_g16[15] = {KSG_R(0),  KSG_R(1),  KSG_R(2),  KSG_R(3),  KSG_R(4),
+                                              KSG_R(5),  KSG_R(6),  KSG_R(7),  KSG_R(8),  KSG_R(9),
+                                              KSG_R(10), KSG_R(11), KSG_R(12), KSG_R(13), KSG_R(14)};
 
 }  // namespace ksg

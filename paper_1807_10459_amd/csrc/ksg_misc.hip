@@ -16,10 +16,13 @@ namespace ksg {
 extern const void* search_kernels_kp5[40];
 extern const void* search_kernels_kp9[40];
 extern const void* search_kernels_kp17[40];
-extern const void* group_kernels_kp5_g8[15];
-extern const void* group_kernels_kp5_g16[15];
-extern const void* group_kernels_kp9_g8[15];
-extern const void* group_kernels_kp9_g16[15];
+extern const void* group_radius_kernels_kp5_g8[15];
+extern const void* group_radius_kernels_kp5_g16[15];
+extern const void* group_radius_kernels_kp9_g8[15];
+extern const void* group_radius_kernels_kp9_g16[15];
+extern const void* group_xcount_kernels_g8[15];
+extern const void* group_xcount_kernels_g16[15];
+extern const void* yzcount_kernels[15];
 
 // ------------------------------------------------------------------ packing
 
@@ -273,20 +276,54 @@ hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, in
   return hipLaunchKernel(fn, dim3(n_items), dim3(kTileQ), args, 0, stream);
 }
 
-hipError_t launch_ksg_group(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
-                            int n_items, const double* d_htab, double* d_partials, int m, int G,
-                            int kp, unsigned long long* d_work, hipStream_t stream) {
+hipError_t launch_ksg_group_radius(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
+                                   int n_items, float* E, int m, int G, int kp,
+                                   unsigned long long* d_work, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
   if (m < 0 || m > 14 || (G != 8 && G != 16) || (kp != 5 && kp != 9)) return hipErrorInvalidValue;
-  const void* const* table = kp == 5 ? (G == 8 ? group_kernels_kp5_g8 : group_kernels_kp5_g16)
-                                     : (G == 8 ? group_kernels_kp9_g8 : group_kernels_kp9_g16);
+  const void* const* table = kp == 5 ? (G == 8 ? group_radius_kernels_kp5_g8 : group_radius_kernels_kp5_g16)
+                                     : (G == 8 ? group_radius_kernels_kp9_g8 : group_radius_kernels_kp9_g16);
   const float* a0 = base;
   const GroupDesc* a1 = d_gdesc;
   const WorkItem* a2 = d_items;
-  const double* a3 = d_htab;
-  double* a4 = d_partials;
-  unsigned long long* a5 = d_work;
-  void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5};
+  float* a3 = E;
+  unsigned long long* a4 = d_work;
+  void* args[] = {&a0, &a1, &a2, &a3, &a4};
+  return hipLaunchKernel(table[m], dim3(n_items), dim3(kTileQ), args, 0, stream);
+}
+
+hipError_t launch_ksg_yzcount(const float* base, const YZDesc* d_ydesc, const WorkItem* d_items,
+                              int n_items, const float* E, double* T, const double* d_htab, int m,
+                              unsigned long long* d_work, hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  if (m < 0 || m > 14) return hipErrorInvalidValue;
+  const float* a0 = base;
+  const YZDesc* a1 = d_ydesc;
+  const WorkItem* a2 = d_items;
+  const float* a3 = E;
+  double* a4 = T;
+  const double* a5 = d_htab;
+  unsigned long long* a6 = d_work;
+  void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6};
+  return hipLaunchKernel(yzcount_kernels[m], dim3(n_items), dim3(256), args, 0, stream);
+}
+
+hipError_t launch_ksg_group_xcount(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
+                                   int n_items, const float* E, const double* T, const double* d_htab,
+                                   double* d_partials, int m, int G, unsigned long long* d_work,
+                                   hipStream_t stream) {
+  if (n_items <= 0) return hipSuccess;
+  if (m < 0 || m > 14 || (G != 8 && G != 16)) return hipErrorInvalidValue;
+  const void* const* table = G == 8 ? group_xcount_kernels_g8 : group_xcount_kernels_g16;
+  const float* a0 = base;
+  const GroupDesc* a1 = d_gdesc;
+  const WorkItem* a2 = d_items;
+  const float* a3 = E;
+  const double* a4 = T;
+  const double* a5 = d_htab;
+  double* a6 = d_partials;
+  unsigned long long* a7 = d_work;
+  void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
   return hipLaunchKernel(table[m], dim3(n_items), dim3(kTileQ), args, 0, stream);
 }
 

@@ -58,6 +58,7 @@ struct ksg_ctx {
   bool use_graph = true;
 
   ksg::DevBuf htab, pool, desc, items, partials, jobs, tmp, embed, cmi, aux, feat;
+  ksg::DevBuf ebuf, tbuf;  // grouped search: radii E (FP32) and Y/Z count terms T (FP64)
   int64_t htab_n = 0;
   int* d_counter = nullptr;  // [1]: finite / permutation-range flag
   int* d_flag = nullptr;
@@ -81,9 +82,17 @@ struct ksg_ctx {
   // KSG_OPT_TIMING: events around each search launch, harvested by ksg_take_timing.
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
+  // per-kernel spans: kind 0 radius, 1 Y/Z count, 2 X count, 3 single-problem search
+  struct Span {
+    hipEvent_t a, b;
+    int kind;
+  };
+  std::vector<Span> spans;
   std::vector<hipEvent_t> event_pool;
   double timed_ops = 0.0;
-  unsigned long long last_work[3] = {0, 0, 0};  // counters read by the last take_timing
+  unsigned long long last_work[5] = {0, 0, 0, 0, 0};  // counters read by the last take_timing
+  double last_kernel_ms[4] = {0, 0, 0, 0}, last_kernel_ops[4] = {0, 0, 0, 0};
+  int64_t last_kernel_launches[4] = {0, 0, 0, 0};
   hipEvent_t get_event();
 
   int fail(int status, const char* fmt, ...);
