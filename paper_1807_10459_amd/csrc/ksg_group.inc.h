@@ -173,10 +173,9 @@ __device__ __forceinline__ void group_radius_tile(const float* __restrict__ base
       d[3] = __builtin_amdgcn_fmed3f(fabsf(rx[g].w - qx[g]), dyz[3], INFINITY);
       const unsigned lo = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
                               min(__float_as_uint(d[2]), __float_as_uint(d[3])));
-      if (lo < __float_as_uint(b[g][KP - 1])) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) topk_insert<KP>(b[g], d[u]);
-      }
+      if (lo < __float_as_uint(b[g][KP - 1]))
+        topk_insert4<KP>(b[g], __float_as_uint(d[0]), __float_as_uint(d[1]), __float_as_uint(d[2]),
+                         __float_as_uint(d[3]));
     }
     bmax = __float_as_uint(b[0][KP - 1]);
 #pragma unroll

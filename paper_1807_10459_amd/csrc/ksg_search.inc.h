@@ -40,6 +40,35 @@ __device__ __forceinline__ void topk_insert(float (&b)[KP], float d) {
   b[0] = __builtin_amdgcn_fmed3f(-INFINITY, b[0], d);
 }
 
+// Insertion of four candidates given as the bit patterns of non-negative floats, for waves in
+// which some lane has a candidate below its radius.  The candidates are inserted in ascending
+// order, and usually only the smallest is below the radius: the three others are inserted only
+// when the second smallest still is, for some lane of the wave.  Inserting the values in order
+// equals inserting the multiset (an insertion of a value >= the radius changes nothing), so the
+// result is that of four plain insertions.  b[0] takes a signed integer minimum of the bit
+// patterns, which orders -inf (an inert slot) below every non-negative value as the FP32
+// minimum does, without the quieting copies an IEEE-mode minimum needs.
+template <int KP>
+__device__ __forceinline__ void topk_insert_sorted(float (&b)[KP], float v) {
+#pragma unroll
+  for (int i = KP - 1; i >= 1; --i) b[i] = __builtin_amdgcn_fmed3f(b[i - 1], b[i], v);
+  b[0] = __int_as_float(min(__float_as_int(b[0]), __float_as_int(v)));
+}
+
+template <int KP>
+__device__ __forceinline__ void topk_insert4(float (&b)[KP], unsigned a0, unsigned a1, unsigned a2,
+                                             unsigned a3) {
+  const unsigned p = min(a0, a1), q = max(a0, a1), r = min(a2, a3), t = max(a2, a3);
+  const unsigned mid_lo = max(p, r), mid_hi = min(q, t);
+  const unsigned s0 = min(p, r), s1 = min(mid_lo, mid_hi);
+  topk_insert_sorted<KP>(b, __uint_as_float(s0));
+  if (__builtin_amdgcn_ballot_w64(s1 < __float_as_uint(b[KP - 1])) != 0) {
+    topk_insert_sorted<KP>(b, __uint_as_float(s1));
+    topk_insert_sorted<KP>(b, __uint_as_float(max(mid_lo, mid_hi)));
+    topk_insert_sorted<KP>(b, __uint_as_float(max(q, t)));
+  }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
