@@ -209,15 +209,62 @@ __device__ __forceinline__ void group_xcount_tile(const float* __restrict__ base
                                                   const double* __restrict__ htab,
                                                   double* __restrict__ partials,
                                                   double (*s_red)[G],
+                                                  unsigned long long* __restrict__ s_ord,
                                                   unsigned long long* __restrict__ work) {
   constexpr int U = 4;
   constexpr int W = M + 1;
   const int n = gd->n;
   const int n_pad = gd->n_pad;
   const int ng = gd->ng;
-  const int qraw = tile * kTileQ + (int)threadIdx.x;
-  const bool valid = qraw < n;
-  const int qi = valid ? qraw : n - 1;
+
+  // Query regrouping: the tile's rows are handed to its four waves in ascending order of
+  // their largest radius (ties by row), so that each wave's window, set by its largest
+  // radius, is not widened by a few wide rows among narrow ones.  The rows of a wave are no
+  // longer consecutive: its own steps span the rows from its smallest to its largest, and
+  // the window scans start beyond them, which keeps the bounds exact.
+  auto load_eps = [&](int row, float (&eps)[G]) {
+    const float* e = E + gd->e_off + (size_t)row * G;
+#pragma unroll
+    for (int g = 0; g < G; g += 4) {
+      const ksg_f4 v = *reinterpret_cast<const ksg_f4*>(e + g);
+      eps[g] = v.x;
+      eps[g + 1] = v.y;
+      eps[g + 2] = v.z;
+      eps[g + 3] = v.w;
+    }
+  };
+  float eps[G];
+  int qi;
+  bool valid;
+  {
+    const int own = tile * kTileQ + (int)threadIdx.x;
+    const bool own_valid = own < n;
+    load_eps(own_valid ? own : n - 1, eps);
+    unsigned em = __float_as_uint(eps[0]);
+#pragma unroll
+    for (int g = 1; g < G; ++g) em = max(em, __float_as_uint(eps[g]));
+    s_ord[threadIdx.x] = own_valid ? ((unsigned long long)em << 32) | (unsigned)own : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= kTileQ; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const int t = threadIdx.x;
+        if (t < kTileQ / 2) {
+          const int lo = 2 * t - (t & (stride - 1));
+          const int hi = lo + stride;
+          const unsigned long long a = s_ord[lo], b = s_ord[hi];
+          if ((a > b) == ((lo & size) == 0)) {
+            s_ord[lo] = b;
+            s_ord[hi] = a;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    const unsigned long long kk = s_ord[threadIdx.x];
+    valid = kk != ~0ull;
+    qi = valid ? (int)(unsigned)(kk & 0xffffffffu) : n - 1;
+    load_eps(qi, eps);
+  }
 
   const float* xi = base + gd->xi_off;
   const float* yzi = base + gd->yzi_off;
@@ -229,20 +276,21 @@ __device__ __forceinline__ void group_xcount_tile(const float* __restrict__ base
   for (int g = 0; g < G; ++g) qx[g] = xi[(qs * G + g) * 4 + ql];
 #pragma unroll
   for (int a = 0; a < M; ++a) qz[a] = yzi[(qs * W + 1 + a) * 4 + ql];
-  float eps[G];
+  const int steps = n_pad / U;
+  WaveRange wr = wave_range(tile, n);
   {
-    const float* e = E + gd->e_off + (size_t)qi * G;
+    // the wave's rows span [rmin, rmax]; invalid lanes (row n-1) only widen it
+    int rmin = qi, rmax = qi;
 #pragma unroll
-    for (int g = 0; g < G; g += 4) {
-      const ksg_f4 v = *reinterpret_cast<const ksg_f4*>(e + g);
-      eps[g] = v.x;
-      eps[g + 1] = v.y;
-      eps[g + 2] = v.z;
-      eps[g + 3] = v.w;
+    for (int off = 32; off >= 1; off >>= 1) {
+      rmin = min(rmin, __shfl_xor(rmin, off, 64));
+      rmax = max(rmax, __shfl_xor(rmax, off, 64));
+    }
+    if (wr.live) {
+      wr.s_lo = __builtin_amdgcn_readfirstlane(rmin) >> 2;
+      wr.s_hi = __builtin_amdgcn_readfirstlane(rmax) >> 2;
     }
   }
-  const int steps = n_pad / U;
-  const WaveRange wr = wave_range(tile, n);
 
   unsigned cxz[G];
 #pragma unroll
@@ -324,14 +372,20 @@ __device__ __forceinline__ void group_xcount_tile(const float* __restrict__ base
   }
 
   // ---- epilogue: self correction, digamma terms, one partial per (problem, tile) ----
+  // The terms go back to their rows' places before the fixed-order sum, so the partial does
+  // not depend on how the rows were handed to the waves (nor on the group size).
   const int wave = threadIdx.x >> 6;
   const double* trow = T + gd->e_off + (size_t)qi * G;
+  double* s_term = reinterpret_cast<double*>(s_ord);
+  const int slot = valid ? qi - tile * kTileQ : (int)threadIdx.x;  // invalid rows sort last
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     const int self = eps[g] > 0.0f ? 1 : 0;
     const int nxz = max((int)cxz[g] - self, 0);
-    double t = valid ? htab[nxz] + trow[g] : 0.0;
-    t = wave_sum(t);
+    __syncthreads();
+    s_term[slot] = valid ? htab[nxz] + trow[g] : 0.0;
+    __syncthreads();
+    const double t = wave_sum(s_term[threadIdx.x]);
     if ((threadIdx.x & 63) == 0) s_red[wave][g] = t;
   }
   if (work && (threadIdx.x & 63) == 0) {
@@ -369,12 +423,13 @@ __global__ __launch_bounds__(kTileQ) void ksg_group_xcount_kernel(const float* _
                                                                   double* __restrict__ partials,
                                                                   unsigned long long* __restrict__ work) {
   __shared__ double s_red[kTileQ / 64][G];
+  __shared__ unsigned long long s_ord[kTileQ];
   const KSG_AS4 WorkItem* i4 = (const KSG_AS4 WorkItem*)items;
   const int grp = i4[blockIdx.x].prob;
   if (grp < 0) return;
   const int tile = i4[blockIdx.x].tile;
   const KSG_AS4 GroupDesc* gd = (const KSG_AS4 GroupDesc*)descs + grp;
-  group_xcount_tile<M, G>(base, gd, tile, E, T, htab, partials, s_red, work);
+  group_xcount_tile<M, G>(base, gd, tile, E, T, htab, partials, s_red, s_ord, work);
 }
 
 }  // namespace ksg
