@@ -66,11 +66,21 @@ __device__ __forceinline__ WaveRange wave_range(int tile, int n) {
 // Exact skips: d(g) = max(|dx_g|, dyz) >= dyz, so when dyz >= radius_g for all four
 // references and every lane of the wave, problem g cannot gain a neighbour in the step; when
 // that holds for bmax = max_g radius_g the whole step is skipped.
+// Two phases.  Phase 1: every wave scans all rows of its tile for its own 64 queries, which
+// leaves each query's top-(k+1) lists over the tile and so an upper bound on each radius.
+// Then the tile's queries are handed to the waves again in ascending order of their largest
+// bound (the lists travel through LDS), so that a wave's window is not widened by a few wide
+// queries among narrow ones.  Phase 2: each wave scans outward from the tile, alternating right
+// and left, with the key window of its current radii.  Every row is examined exactly once per
+// query, so the radii are those of a full scan.
 // Output: E[e_off + row * G + g] = eps of problem g at (key-ordered) row, rows < n.
+constexpr int kXchg = 20;  // floats per lane per LDS exchange round
 template <int M, int G, int KP>
 __device__ __forceinline__ void group_radius_tile(const float* __restrict__ base,
                                                   const KSG_AS4 GroupDesc* gd, int tile,
                                                   float* __restrict__ E,
+                                                  unsigned long long* __restrict__ s_ord,
+                                                  float (*s_x)[kTileQ],
                                                   unsigned long long* __restrict__ work) {
   constexpr int U = 4;
   constexpr int W = M + 1;
@@ -79,24 +89,27 @@ __device__ __forceinline__ void group_radius_tile(const float* __restrict__ base
   const int n_pad = gd->n_pad;
   const int k = gd->k;
   const int ng = gd->ng;
-  const int qraw = tile * kTileQ + (int)threadIdx.x;
-  const bool valid = qraw < n;
-  const int qi = valid ? qraw : n - 1;
+  const int tid = (int)threadIdx.x;
+  int qi = min(tile * kTileQ + tid, n - 1);
+  bool valid = tile * kTileQ + tid < n;
 
   const float* xi = base + gd->xi_off;
   const float* yzi = base + gd->yzi_off;
   const cf4ptr px = (cf4ptr)xi;
   const cf4ptr pyz = (cf4ptr)yzi;
-  float qx[G], qz[M > 0 ? M : 1];
-  const int qs = qi >> 2, ql = qi & 3;
+  float qx[G], qz[M > 0 ? M : 1], qy, qkey;
+  auto load_query = [&]() {
+    const int qs = qi >> 2, ql = qi & 3;
 #pragma unroll
-  for (int g = 0; g < G; ++g) qx[g] = xi[(qs * G + g) * 4 + ql];
-  const float qy = yzi[(qs * W) * 4 + ql];
+    for (int g = 0; g < G; ++g) qx[g] = xi[(qs * G + g) * 4 + ql];
+    qy = yzi[(qs * W) * 4 + ql];
 #pragma unroll
-  for (int a = 0; a < M; ++a) qz[a] = yzi[(qs * W + 1 + a) * 4 + ql];
+    for (int a = 0; a < M; ++a) qz[a] = yzi[(qs * W + 1 + a) * 4 + ql];
+    qkey = M > 0 ? qz[0] : qy;
+  };
+  load_query();
   const int steps = n_pad / U;
   const WaveRange wr = wave_range(tile, n);
-  const float qkey = M > 0 ? qz[0] : qy;
 
   float b[G][KP];
 #pragma unroll
@@ -107,22 +120,10 @@ __device__ __forceinline__ void group_radius_tile(const float* __restrict__ base
   unsigned bmax = __float_as_uint(INFINITY);
   unsigned done = 0;    // problem-steps whose per-problem work ran (wave-uniform)
   unsigned shared = 0;  // shared-part operations / 256 (wave-uniform)
-  int own = wr.s_lo, r = wr.s_hi + 1, l = wr.s_lo - 1;
-  bool ract = wr.live && r < steps, lact = wr.live && l >= 0, right_turn = true;
-  for (;;) {
-    int s, dir;
-    if (own <= wr.s_hi) {
-      s = own++;
-      dir = 0;
-    } else if (ract && (right_turn || !lact)) {
-      s = r;
-      dir = 1;
-    } else if (lact) {
-      s = l;
-      dir = -1;
-    } else {
-      break;
-    }
+
+  // One reference step s; dir != 0: a window step, skipped (returns true) when every lane's
+  // key gap reaches its bound.
+  auto step = [&](int s, int dir) -> bool {
     // the step's X block is requested first so that its latency overlaps the Y/Z work
     ksg_f4 rx[G];
 #pragma unroll
@@ -134,14 +135,7 @@ __device__ __forceinline__ void group_radius_tile(const float* __restrict__ base
     float dyz[U] = {fabsf(rk.x - qkey), fabsf(rk.y - qkey), fabsf(rk.z - qkey), fabsf(rk.w - qkey)};
     if (dir != 0) {
       const float gap = dir > 0 ? dyz[0] : dyz[3];
-      if (__builtin_amdgcn_ballot_w64(__float_as_uint(gap) < bmax) == 0) {
-        if (dir > 0) ract = false;
-        else lact = false;
-        continue;
-      }
-      if (dir > 0) ract = ++r < steps;
-      else lact = --l >= 0;
-      right_turn = !right_turn;
+      if (__builtin_amdgcn_ballot_w64(__float_as_uint(gap) < bmax) == 0) return true;
     }
     shared += 2 * M + 2;
     if constexpr (M > 0) {
@@ -161,7 +155,7 @@ __device__ __forceinline__ void group_radius_tile(const float* __restrict__ base
     }
     const unsigned dmin = min(min(__float_as_uint(dyz[0]), __float_as_uint(dyz[1])),
                               min(__float_as_uint(dyz[2]), __float_as_uint(dyz[3])));
-    if (__builtin_amdgcn_ballot_w64(dmin < bmax) == 0) continue;
+    if (__builtin_amdgcn_ballot_w64(dmin < bmax) == 0) return false;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if (__builtin_amdgcn_ballot_w64(dmin < __float_as_uint(b[g][KP - 1])) == 0) continue;
@@ -180,6 +174,86 @@ __device__ __forceinline__ void group_radius_tile(const float* __restrict__ base
     bmax = __float_as_uint(b[0][KP - 1]);
 #pragma unroll
     for (int g = 1; g < G; ++g) bmax = max(bmax, __float_as_uint(b[g][KP - 1]));
+    return false;
+  };
+
+  // ---- phase 1: the tile's own rows ----
+  const int t_lo = tile * (kTileQ / U);                    // first step of the tile
+  const int t_hi = min(t_lo + kTileQ / U, (n + U - 1) / U) - 1;  // last step holding real rows
+  if (wr.live)
+    for (int s = t_lo; s <= t_hi; ++s) step(s, 0);
+
+  // ---- regroup the tile's queries by their largest bound ----
+  {
+    unsigned ub = __float_as_uint(b[0][KP - 1]);
+#pragma unroll
+    for (int g = 1; g < G; ++g) ub = max(ub, __float_as_uint(b[g][KP - 1]));
+    s_ord[tid] = valid ? ((unsigned long long)ub << 32) | (unsigned)qi : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= kTileQ; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        if (tid < kTileQ / 2) {
+          const int lo = 2 * tid - (tid & (stride - 1));
+          const int hi = lo + stride;
+          const unsigned long long a = s_ord[lo], c = s_ord[hi];
+          if ((a > c) == ((lo & size) == 0)) {
+            s_ord[lo] = c;
+            s_ord[hi] = a;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    const unsigned long long kk = s_ord[tid];
+    const bool nvalid = kk != ~0ull;
+    const int nrow = nvalid ? (int)(unsigned)(kk & 0xffffffffu) : n - 1;
+    const int src = nvalid ? nrow - tile * kTileQ : tid;  // lane that held the row's lists
+    constexpr int PR = kXchg / KP;                         // problems per exchange round
+#pragma unroll
+    for (int g0 = 0; g0 < G; g0 += PR) {
+#pragma unroll
+      for (int g = g0; g < g0 + PR && g < G; ++g)
+#pragma unroll
+        for (int i = 0; i < KP; ++i) s_x[(g - g0) * KP + i][tid] = b[g][i];
+      __syncthreads();
+#pragma unroll
+      for (int g = g0; g < g0 + PR && g < G; ++g)
+#pragma unroll
+        for (int i = 0; i < KP; ++i) b[g][i] = s_x[(g - g0) * KP + i][src];
+      __syncthreads();
+    }
+    valid = nvalid;
+    qi = nrow;
+    load_query();
+    bmax = __float_as_uint(b[0][KP - 1]);
+#pragma unroll
+    for (int g = 1; g < G; ++g) bmax = max(bmax, __float_as_uint(b[g][KP - 1]));
+  }
+
+  // ---- phase 2: outward from the tile, alternating right and left ----
+  {
+    int r = t_hi + 1, l = t_lo - 1;
+    bool ract = wr.live && r < steps, lact = wr.live && l >= 0, right_turn = true;
+    for (;;) {
+      int s, dir;
+      if (ract && (right_turn || !lact)) {
+        s = r;
+        dir = 1;
+      } else if (lact) {
+        s = l;
+        dir = -1;
+      } else {
+        break;
+      }
+      if (step(s, dir)) {
+        if (dir > 0) ract = false;
+        else lact = false;
+        continue;
+      }
+      if (dir > 0) ract = ++r < steps;
+      else lact = --l >= 0;
+      right_turn = !right_turn;
+    }
   }
 
   if (valid) {
@@ -405,12 +479,14 @@ __global__ __launch_bounds__(kTileQ) void ksg_group_radius_kernel(const float* _
                                                                   const WorkItem* __restrict__ items,
                                                                   float* __restrict__ E,
                                                                   unsigned long long* __restrict__ work) {
+  __shared__ unsigned long long s_ord[kTileQ];
+  __shared__ float s_x[kXchg][kTileQ];
   const KSG_AS4 WorkItem* i4 = (const KSG_AS4 WorkItem*)items;
   const int grp = i4[blockIdx.x].prob;
   if (grp < 0) return;
   const int tile = i4[blockIdx.x].tile;
   const KSG_AS4 GroupDesc* gd = (const KSG_AS4 GroupDesc*)descs + grp;
-  group_radius_tile<M, G, KP>(base, gd, tile, E, work);
+  group_radius_tile<M, G, KP>(base, gd, tile, E, s_ord, s_x, work);
 }
 
 template <int M, int G>
