@@ -66,8 +66,9 @@ __device__ __forceinline__ WaveRange wave_range(int tile, int n) {
 // Exact skips: d(g) = max(|dx_g|, dyz) >= dyz, so when dyz >= radius_g for all four
 // references and every lane of the wave, problem g cannot gain a neighbour in the step; when
 // that holds for bmax = max_g radius_g the whole step is skipped.
-// Two phases.  Phase 1: every wave scans all rows of its tile for its own 64 queries, which
-// leaves each query's top-(k+1) lists over the tile and so an upper bound on each radius.
+// Two phases.  Phase 1: every wave scans all rows of its tile and of the two neighbouring
+// tiles for its own 64 queries, which leaves each query's top-(k+1) lists over those rows and
+// so an upper bound on each radius.
 // Then the tile's queries are handed to the waves again in ascending order of their largest
 // bound (the lists travel through LDS), so that a wave's window is not widened by a few wide
 // queries among narrow ones.  Phase 2: each wave scans outward from the tile, alternating right
@@ -177,9 +178,10 @@ __device__ __forceinline__ void group_radius_tile(const float* __restrict__ base
     return false;
   };
 
-  // ---- phase 1: the tile's own rows ----
-  const int t_lo = tile * (kTileQ / U);                    // first step of the tile
-  const int t_hi = min(t_lo + kTileQ / U, (n + U - 1) / U) - 1;  // last step holding real rows
+  // ---- phase 1: the tile's rows and those of its two neighbouring tiles ----
+  const int real_steps = (n + U - 1) / U;                  // steps holding real rows
+  const int t_lo = max(tile * (kTileQ / U) - kTileQ / U, 0);
+  const int t_hi = min(tile * (kTileQ / U) + 2 * (kTileQ / U), real_steps) - 1;
   if (wr.live)
     for (int s = t_lo; s <= t_hi; ++s) step(s, 0);
 
