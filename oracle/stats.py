@@ -19,7 +19,27 @@ gives no formulas; the readings taken here are:
   the test is significant; stop at the first non-significant step or when
   the pool is empty;
 * omnibus: I(selected source candidates ; Y | selected target-past
-  candidates), surrogates permute the rows of the whole source block.
+  candidates), surrogates permute the rows of the whole source block;
+* the conditioning set is capped at 14 columns (16 dimensions with X and Y):
+  a selection stops when it is full.
+
+The paper's network paragraph also names bivariate and multivariate
+variants and post-selection statistics without defining them; the readings
+taken here (network_select, min_statistic, prune_min_statistic, fdr_bh):
+
+* multivariate TE: one pool of every variable's past (the default above);
+* multivariate MI: the same without the target's own past;
+* bivariate TE: first the target's own past alone, then each source on its
+  own (sources in index order), its lags conditioned only on the selected
+  target past and that source's own selected lags;
+* min-statistic pruning of the selected sources: each selected source c
+  gets I(c ; Y | every other selected candidate) and its surrogates (c's
+  rows permuted, one permutation per round shared by all c); T_min = min_c
+  (lowest index on ties), per-round minima T_p; p = #{p : T_p >= T_min}/P;
+  if p >= alpha the minimising source is removed and the test repeats,
+  otherwise every remaining source is kept;
+* FDR across targets: Benjamini-Hochberg at level alpha on the targets'
+  omnibus p-values.
 """
 from __future__ import annotations
 
@@ -37,7 +57,14 @@ __all__ = [
     "order_statistic_threshold",
     "greedy_select",
     "omnibus_test",
+    "network_select",
+    "MinStat",
+    "min_statistic",
+    "prune_min_statistic",
+    "fdr_bh",
 ]
+
+MAX_COND = 14  # conditioning columns: 16 dimensions with X and Y
 
 
 def embed(data, target: int, max_lag: int):
@@ -107,18 +134,22 @@ def _step_cmis(cand, y, zcols, pool, perms, k):
 
 
 def greedy_select(cand, y, k: int, perms, alpha: float = 0.05, max_steps: int | None = None,
-                  return_cmis: bool = False):
+                  return_cmis: bool = False, pool=None, selected=None):
     """Greedy CMI-maximising selection gated by the max-statistic test.
 
-    cand: [C][N] FP32 candidate columns, y: [N] FP32, perms: int [P][N].
-    Returns (selected candidate indices in inclusion order, per-step MaxStat list[, per-step CMI tables]).
+    cand: [C][N] FP32 candidate columns, y: [N] FP32, perms: int [P][N].  pool: candidate
+    indices to choose from (default: all); selected: the initial conditioning set (default:
+    empty), extended in place of a copy.
+    Returns (selected candidate indices in inclusion order, per-step MaxStat list[, per-step
+    CMI tables]); the returned selection starts with the initial set.
     """
     cand = np.asarray(cand, dtype=np.float32)
     y = np.asarray(y, dtype=np.float32)
     perms = np.asarray(perms)
-    pool = list(range(cand.shape[0]))
-    selected, steps, tables = [], [], []
-    while pool and (max_steps is None or len(steps) < max_steps):
+    pool = list(range(cand.shape[0])) if pool is None else list(pool)
+    selected = [] if selected is None else list(selected)
+    steps, tables = [], []
+    while pool and len(selected) < MAX_COND and (max_steps is None or len(steps) < max_steps):
         cmis = _step_cmis(cand, y, [cand[s] for s in selected], pool, perms, k)
         ms = max_statistic(cmis, alpha)
         steps.append(ms)
@@ -152,3 +183,99 @@ def omnibus_test(cand, y, selected, target: int, max_lag: int, k: int, perms,
     for p in range(P):
         out[0, p + 1] = ksg_cmi(xs[perms[p]], y, z, k)
     return out, max_statistic(out, alpha)
+
+
+def network_select(cand, y, target: int, max_lag: int, k: int, perms, alpha: float = 0.05,
+                   mode: str = "mte"):
+    """Parents of one target: mode "mte" (multivariate TE), "mmi" (multivariate MI) or "bte"
+    (bivariate TE), readings in the module docstring.
+    Returns (selected candidate indices in inclusion order, per-step MaxStat list)."""
+    C = np.asarray(cand).shape[0]
+    L = max_lag
+    own = [c for c in range(C) if c // L == target]
+    if mode == "mte":
+        return greedy_select(cand, y, k, perms, alpha)
+    if mode == "mmi":
+        return greedy_select(cand, y, k, perms, alpha, pool=[c for c in range(C) if c // L != target])
+    if mode != "bte":
+        raise ValueError(mode)
+    tgt, steps = greedy_select(cand, y, k, perms, alpha, pool=own)
+    selected = list(tgt)
+    for v in range(C // L):
+        if v == target:
+            continue
+        sel_v, st_v = greedy_select(cand, y, k, perms, alpha, pool=[v * L + l for l in range(L)],
+                                    selected=tgt)
+        selected += sel_v[len(tgt):]
+        steps += st_v
+    return selected, steps
+
+
+@dataclasses.dataclass
+class MinStat:
+    c_min: int
+    t_min: float
+    count: int
+    pval: float
+    significant: bool
+
+
+def min_statistic(cmi: np.ndarray, alpha: float = 0.05) -> MinStat:
+    """cmi: FP64 [c][P+1] (column 0 originals).  T_min = min_c (lowest index wins ties), per-round
+    minima T_p, p = #{p : T_p >= T_min}/P, significant iff p < alpha."""
+    cmi = np.asarray(cmi, dtype=np.float64)
+    orig = cmi[:, 0]
+    c_min = 0
+    for c in range(1, orig.size):
+        if orig[c] < orig[c_min]:
+            c_min = c
+    t_min = float(orig[c_min])
+    t_p = cmi[:, 1:].min(axis=0)
+    count = int(sum(1 for t in t_p if t >= t_min))
+    pval = count / t_p.size
+    return MinStat(c_min, t_min, count, pval, bool(pval < alpha))
+
+
+def prune_min_statistic(cand, y, selected, target: int, max_lag: int, k: int, perms,
+                        alpha: float = 0.05):
+    """Min-statistic pruning of the selected sources.  Returns (kept selection in the original
+    order, removed candidates in removal order, per-round MinStat list)."""
+    cand = np.asarray(cand, dtype=np.float32)
+    y = np.asarray(y, dtype=np.float32)
+    perms = np.asarray(perms)
+    kept = list(selected)
+    removed, rounds = [], []
+    while True:
+        src = [c for c in kept if c // max_lag != target]
+        if not src:
+            break
+        P = perms.shape[0]
+        table = np.empty((len(src), P + 1))
+        for i, c in enumerate(src):
+            others = [cand[o] for o in kept if o != c]
+            z = np.stack(others, axis=1) if others else np.zeros((y.size, 0), np.float32)
+            table[i, 0] = ksg_cmi(cand[c], y, z, k)
+            for p in range(P):
+                table[i, p + 1] = ksg_cmi(cand[c][perms[p]], y, z, k)
+        ms = min_statistic(table, alpha)
+        rounds.append(ms)
+        if ms.significant:
+            break
+        removed.append(src[ms.c_min])
+        kept.remove(src[ms.c_min])
+    return kept, removed, rounds
+
+
+def fdr_bh(pvals, alpha: float = 0.05) -> np.ndarray:
+    """Benjamini-Hochberg: reject the hypotheses with the r smallest p-values, r the largest rank
+    with p_(r) <= r * alpha / m.  Returns a boolean array in the input order."""
+    p = np.asarray(pvals, dtype=np.float64)
+    m = p.size
+    order = np.argsort(p, kind="stable")
+    r = 0
+    for i, idx in enumerate(order, start=1):
+        if p[idx] <= i * alpha / m:
+            r = i
+    out = np.zeros(m, dtype=bool)
+    out[order[:r]] = True
+    return out

@@ -115,3 +115,92 @@ def test_omnibus():
     assert tab[0, 0] == ksg_cmi(cand[2], y, cand[6], 4)
     assert ms.significant
     assert omnibus_test(cand, y, [6], 3, 2, 4, perms) is None
+
+
+# ---- selection modes, min-statistic pruning, FDR (readings in oracle.stats) ----
+
+def _copy_chain(seed, T=170, n_trials=2):
+    """Target 3 driven by source 0 at lag 1 with an autoregressive own past; source 1 is a
+    near-copy of source 0 (redundant given it); source 2 is noise."""
+    g = workloads.rng(seed)
+    x = g.standard_normal((n_trials, 4, T))
+    x[:, 1] = x[:, 0] + 0.05 * g.standard_normal((n_trials, T))
+    for tr in range(n_trials):
+        for t in range(1, T):
+            x[tr, 3, t] = 0.9 * x[tr, 0, t - 1] + 0.5 * x[tr, 3, t - 1] + 0.3 * g.standard_normal()
+    return x.astype(np.float32)
+
+
+def test_selection_modes_on_redundant_sources():
+    """Multivariate TE keeps one of two redundant copies of the driver; bivariate TE, which
+    conditions each source only on the target's past, finds both; multivariate MI never
+    selects the target's own past and, like multivariate TE, keeps one copy."""
+    from oracle.stats import network_select
+    data = _copy_chain(7)
+    L = 1
+    cand, y = embed(data, target=3, max_lag=L)  # candidates: var v at lag 1 -> index v
+    perms = workloads.permutations(y.size, 39, seed=8)
+    mte, _ = network_select(cand, y, 3, L, 4, perms, mode="mte")
+    bte, _ = network_select(cand, y, 3, L, 4, perms, mode="bte")
+    mmi, _ = network_select(cand, y, 3, L, 4, perms, mode="mmi")
+    assert 3 in mte and len({0, 1} & set(mte)) == 1 and 2 not in mte
+    assert 3 in bte and {0, 1} <= set(bte) and 2 not in bte
+    assert bte[0] == 3  # the target's past comes first
+    assert 3 not in mmi and len({0, 1} & set(mmi)) == 1
+
+
+def test_bivariate_first_phase_is_restricted_greedy():
+    from oracle.stats import network_select
+    data = _copy_chain(9)
+    cand, y = embed(data, target=3, max_lag=2)
+    perms = workloads.permutations(y.size, 19, seed=10)
+    sel, steps = network_select(cand, y, 3, 2, 4, perms, mode="bte")
+    own, own_steps = greedy_select(cand, y, 4, perms, pool=[6, 7])
+    assert sel[:len(own)] == own
+    assert steps[0].t_obs == own_steps[0].t_obs
+
+
+def test_min_statistic_hand_example():
+    from oracle.stats import min_statistic
+    # originals 0.5 and 0.3: T_min = 0.3 (candidate 1); round minima 0.1 and 0.1 -> p = 0
+    t = np.array([[0.5, 0.1, 0.6], [0.3, 0.2, 0.1]])
+    ms = min_statistic(t, 0.05)
+    assert (ms.c_min, ms.t_min, ms.count, ms.pval, ms.significant) == (1, 0.3, 0, 0.0, True)
+    # ties in the originals: the lowest index; round minima 0.4 and 0.2 -> one >= 0.3
+    t2 = np.array([[0.3, 0.4, 0.9], [0.3, 0.8, 0.2]])
+    ms2 = min_statistic(t2, 0.6)
+    assert (ms2.c_min, ms2.count, ms2.pval, ms2.significant) == (0, 1, 0.5, True)
+
+
+def test_min_statistic_single_candidate_equals_max_statistic():
+    """With one candidate, min and max statistics are the same permutation test."""
+    from oracle.stats import min_statistic
+    g = workloads.rng(11)
+    for _ in range(50):
+        t = g.standard_normal((1, 21))
+        a, b = min_statistic(t, 0.05), max_statistic(t, 0.05)
+        assert a.pval == b.pval and a.significant == b.significant
+
+
+def test_pruning_removes_a_forced_noise_candidate():
+    from oracle.stats import prune_min_statistic
+    data = _copy_chain(12)
+    L = 1
+    cand, y = embed(data, target=3, max_lag=L)
+    perms = workloads.permutations(y.size, 39, seed=13)
+    kept, removed, rounds = prune_min_statistic(cand, y, [3, 0, 2], 3, L, 4, perms)
+    assert removed == [2] and kept == [3, 0]
+    assert not rounds[0].significant and rounds[-1].significant
+
+
+def test_fdr_bh_matches_library():
+    from scipy.stats import false_discovery_control
+    from oracle.stats import fdr_bh
+    g = workloads.rng(14)
+    for _ in range(200):
+        m = int(g.integers(1, 30))
+        p = np.where(g.random(m) < 0.3, g.random(m) * 0.01, g.random(m))
+        alpha = float(g.choice([0.01, 0.05, 0.2]))
+        ref = false_discovery_control(p, method="bh") <= alpha
+        assert np.array_equal(fdr_bh(p, alpha), ref)
+    assert fdr_bh([0.01, 0.04, 0.03, 0.2], 0.05).tolist() == [True, False, False, False]
