@@ -259,7 +259,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--group-size", type=int, default=-1,
                     help="problems searched together (-1 tuned, 0 off, 8, 16)")
-    ap.add_argument("--workload", default="ar2", choices=["ar2", "c4"],
+    ap.add_argument("--workload", default="ar2", choices=["ar2", "c4", "modes"],
                     help="ar2: CMI/s on the AR(2) forced path (default); c4: learned vs plain null")
     ap.add_argument("--targets", default=None, help="c4: comma-separated targets (default all 20)")
     ap.add_argument("--dataset", default=None, help="c4: load the training set from this npz")
@@ -294,6 +294,33 @@ def main():
         ctx = ksg.Context(0)
         line = c4_evaluate(ctx, args, log=lambda m: print(m, file=sys.stderr, flush=True))
         print(json.dumps(line))
+        return
+
+    if args.workload == "modes":  # the selection variants on the AR(2) network, target 0
+        ctx = ksg.Context(0)
+        net = workloads.ar2_network(seed=1)
+        N = net.data.shape[2] - MAX_LAG
+        data = torch.from_numpy(net.data).cuda()
+        perms = torch.from_numpy(workloads.permutations(N, N_PERM, seed=11)).cuda()
+        ctx.autotune(8192)
+        ctx.select_parents(data, 0, perms, k=K, max_lag=MAX_LAG, max_steps=1)  # warm-up
+        true_src = sorted({s_ for (s_, t_, _) in net.edges if t_ == 0})
+        out = {}
+        for mode, prune in (("mte", False), ("mte", True), ("bte", False), ("mmi", False)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.select_parents(data, 0, perms, k=K, max_lag=MAX_LAG, mode=mode, prune=prune, omnibus=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            srcs = sorted({v for (v, _) in r["parents"] if v != 0})
+            out[mode + ("+prune" if prune else "")] = {
+                "seconds": round(dt, 3), "cmi_per_s": round(r["n_cmi"] / dt, 1), "n_cmi": r["n_cmi"],
+                "steps": r["n_steps"], "parents": r["parents"], "pruned": r["pruned"],
+                "source_vars": srcs, "omnibus_pval": r["omnibus_pval"]}
+            print(f"{mode} prune={prune}: {dt:.2f} s, {r['n_cmi']} CMIs, parents {r['parents']}",
+                  file=sys.stderr, flush=True)
+        print(json.dumps({"workload": "selection variants, AR(2) 5-node network, target 0, N=10000, "
+                                      "k=4, 200 surrogates", "true_source_vars": true_src, "runs": out}))
         return
 
     if args.dump_dataset:

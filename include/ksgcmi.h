@@ -239,8 +239,8 @@ int ksg_greedy_step(ksg_ctx* ctx, const float* cand, const float* y, int64_t N, 
 
 /* ---------------------------------------------------------------------------
  * Greedy parent selection for one target (Summary, network-inference paragraph).
- * Candidates: every variable's past (the target's own included) at lags
- * 1..max_lag, index v*max_lag + (lag-1), one pool.  Each step estimates the CMI
+ * Candidates (mode KSG_MODE_MULTIVARIATE_TE): every variable's past (the target's own
+ * included) at lags 1..max_lag, index v*max_lag + (lag-1), one pool.  Each step estimates the CMI
  * of every remaining candidate and its n_perm surrogates given the selected set
  * in one batched launch, applies the max-statistic test and either includes the
  * argmax (significant) or stops.  perms: device int32 [n_perm][N] row
@@ -248,6 +248,21 @@ int ksg_greedy_step(ksg_ctx* ctx, const float* cand, const float* y, int64_t N, 
  * every candidate.  With omnibus = 1 the final source set is tested jointly:
  * I(selected sources ; Y | selected target past), surrogates permuting the
  * source block rows.
+ *
+ * The conditioning set holds at most 14 columns (16 dimensions with X and Y); a selection
+ * that fills it stops.
+ *
+ * Variants named beside multivariate TE in the same paragraph (readings, the paper defines
+ * neither): KSG_MODE_MULTIVARIATE_MI: the pool without the target's own past;
+ * KSG_MODE_BIVARIATE_TE: first the target's own past alone, then each source in index order
+ * on its own, its lags conditioned only on the selected target past and its own selected lags.
+ *
+ * Post-selection pruning (prune = 1; the problem paragraph's control of errors over many
+ * sources): each selected source c gets I(c ; Y | every other selected candidate) and its
+ * surrogates (c's rows permuted by perms, shared by all c); with T_min the smallest (lowest
+ * index on ties) and T_p the per-round minima, p = #{p : T_p >= T_min}/n_perm; if p >= alpha
+ * the minimising source is removed and the test repeats, else the rest are kept.  The
+ * omnibus test, when asked for, runs on the pruned set.
  *
  * Learned null: learned != NULL gates each step first with the threshold
  * network (ksg_mlp) evaluated on the step's feature vector; only steps whose
@@ -269,7 +284,11 @@ typedef struct ksg_select_opts {
   double margin_hi;
   int32_t judge;
   int32_t max_steps; /* 0 = until the test stops or the pool is empty */
+  int32_t mode;      /* KSG_MODE_* */
+  int32_t prune;     /* 1: min-statistic pruning of the selected sources */
 } ksg_select_opts;
+
+enum { KSG_MODE_MULTIVARIATE_TE = 0, KSG_MODE_BIVARIATE_TE = 1, KSG_MODE_MULTIVARIATE_MI = 2 };
 
 /* Per-step record (host arrays of `capacity` entries, caller-allocated; any may be NULL). */
 typedef struct ksg_parent_set {
@@ -297,6 +316,10 @@ typedef struct ksg_parent_set {
   float* step_pred;
   int32_t* step_verdict;
   int32_t* step_plain;
+  /* Pruning: candidates removed (v*max_lag + lag-1, removal order; host array of capacity
+   * entries or NULL) and how many; var/lag/cmi/pval above hold the kept parents. */
+  int32_t n_pruned;
+  int32_t* pruned;
 } ksg_parent_set;
 
 /* data: device FP32 [n_trials][n_vars][T].  out: host struct.
@@ -304,6 +327,12 @@ typedef struct ksg_parent_set {
  * KSG_EBUFSMALL (more parents than capacity; out->n holds the number needed). */
 int select_parents(ksg_ctx* ctx, const float* data, int32_t n_vars, int64_t T, int32_t n_trials,
                    int32_t target, const ksg_select_opts* opts, ksg_parent_set* out);
+
+/* False discovery rate across targets (network-inference paragraph; reading: Benjamini-
+ * Hochberg at level alpha on the targets' omnibus p-values): reject[i] = 1 for the r smallest
+ * p-values, r the largest rank with p_(r) <= r * alpha / n (ties in index order), else 0.
+ * Host arrays of n entries.  Errors: KSG_EINVAL (null pointers, n < 0, alpha outside (0,1)). */
+int ksg_fdr_bh(const double* pvals, int32_t n, double alpha, int32_t* reject);
 
 /* ---------------------------------------------------------------------------
  * Learned null: a 16-64-64-2 perceptron (ReLU hidden layers, BF16 parameters,

@@ -15,6 +15,7 @@ from ._binding import (  # noqa: F401
     KsgError,
     Problem,
     ThresholdNet,
+    fdr_bh,
     harmonic_table,
     lib,
     lib_path,

@@ -44,7 +44,7 @@ class _SelectOpts(C.Structure):
     _fields_ = [("k", C.c_int32), ("max_lag", C.c_int32), ("n_perm", C.c_int32),
                 ("omnibus", C.c_int32), ("alpha", C.c_double), ("perms", C.c_void_p),
                 ("learned", C.c_void_p), ("margin_lo", C.c_double), ("margin_hi", C.c_double),
-                ("judge", C.c_int32), ("max_steps", C.c_int32)]
+                ("judge", C.c_int32), ("max_steps", C.c_int32), ("mode", C.c_int32), ("prune", C.c_int32)]
 
 
 class _ParentSet(C.Structure):
@@ -54,7 +54,8 @@ class _ParentSet(C.Structure):
                 ("omnibus_tested", C.c_int32), ("omnibus_significant", C.c_int32),
                 ("omnibus_cmi", C.c_double), ("omnibus_pval", C.c_double), ("n_cmi", C.c_int64),
                 ("step_capacity", C.c_int32), ("step_tobs", C.c_void_p), ("step_pred", C.c_void_p),
-                ("step_verdict", C.c_void_p), ("step_plain", C.c_void_p)]
+                ("step_verdict", C.c_void_p), ("step_plain", C.c_void_p), ("n_pruned", C.c_int32),
+                ("pruned", C.c_void_p)]
 
 
 def _load():
@@ -101,6 +102,7 @@ def _load():
         "ksg_gate_calibrate": ([vp, vp, vp, vp, i64, d, C.POINTER(d), C.POINTER(d), C.POINTER(d),
                                 C.POINTER(i64)], i32),
         "ksg_step_features": ([vp, vp, i32, vp, vp, i64, vp, i32, i32, i32, i32, i32, vp], i32),
+        "ksg_fdr_bh": ([vp, i32, d, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -122,6 +124,19 @@ def harmonic_table(nmax: int) -> np.ndarray:
     if st:
         raise KsgError(st, "ksg_harmonic_table")
     return out
+
+
+def fdr_bh(pvals, alpha: float = 0.05) -> np.ndarray:
+    """Benjamini-Hochberg decisions across targets (see ksg_fdr_bh)."""
+    p = np.ascontiguousarray(np.asarray(pvals, dtype=np.float64))
+    out = np.zeros(p.size, np.int32)
+    st = lib.ksg_fdr_bh(p.ctypes.data, p.size, float(alpha), out.ctypes.data)
+    if st:
+        raise KsgError(st, "ksg_fdr_bh")
+    return out.astype(bool)
+
+
+MODES = {"mte": 0, "bte": 1, "mmi": 2}
 
 
 def _ptr(t) -> Optional[int]:
@@ -310,14 +325,17 @@ class Context:
     def select_parents(self, data, target: int, perms, k: int = 4, max_lag: int = 5,
                        alpha: float = 0.05, omnibus: bool = False, learned: "ThresholdNet" = None,
                        margin_lo: float = 1.0, margin_hi: float = 1.0, judge: bool = False,
-                       max_steps: int = 0, capacity: int = 64) -> dict:
+                       max_steps: int = 0, capacity: int = 64, mode: str = "mte",
+                       prune: bool = False) -> dict:
+        """Parents of one target.  mode: "mte" (multivariate TE), "bte" (bivariate TE) or "mmi"
+        (multivariate MI); prune: min-statistic pruning of the selected sources."""
         import torch
         _check_dtype(data, torch.float32, "data")
         _check_dtype(perms, torch.int32, "perms")
         n_trials, n_vars, T = data.shape
         opts = _SelectOpts(int(k), int(max_lag), int(perms.shape[0]), int(bool(omnibus)), float(alpha),
                            _ptr(perms), learned._h if learned is not None else None, float(margin_lo),
-                           float(margin_hi), int(bool(judge)), int(max_steps))
+                           float(margin_hi), int(bool(judge)), int(max_steps), MODES[mode], int(bool(prune)))
         var = np.zeros(capacity, np.int32)
         lag = np.zeros(capacity, np.int32)
         cmi = np.zeros(capacity, np.float64)
@@ -331,6 +349,8 @@ class Context:
         ps.step_capacity = scap
         ps.step_tobs, ps.step_pred = s_t.ctypes.data, s_p.ctypes.data
         ps.step_verdict, ps.step_plain = s_v.ctypes.data, s_pl.ctypes.data
+        prn = np.zeros(capacity, np.int32)
+        ps.pruned = prn.ctypes.data
         self._check(lib.select_parents(self._h, _ptr(data), n_vars, T, n_trials, int(target),
                                        C.byref(opts), C.byref(ps)), "select_parents")
         n = ps.n
@@ -341,6 +361,7 @@ class Context:
                     n_gate_decided=ps.n_gate_decided, omnibus_tested=bool(ps.omnibus_tested),
                     omnibus_significant=bool(ps.omnibus_significant), omnibus_cmi=ps.omnibus_cmi,
                     omnibus_pval=ps.omnibus_pval, n_cmi=ps.n_cmi,
+                    pruned=[int(v) for v in prn[:min(ps.n_pruned, capacity)]],
                     steps=[dict(t_obs=float(s_t[i]), pred=[float(s_p[i, 0]), float(s_p[i, 1])],
                                 verdict=int(s_v[i]), plain=int(s_pl[i]))
                            for i in range(min(ps.n_steps, scap))])

@@ -78,6 +78,8 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   if (out->capacity < 0) return c->fail(KSG_EINVAL, "select_parents: negative capacity");
   if (o->learned && !(o->margin_lo >= 0 && o->margin_hi >= 0))
     return c->fail(KSG_EINVAL, "select_parents: margins must be >= 0");
+  if (o->mode < KSG_MODE_MULTIVARIATE_TE || o->mode > KSG_MODE_MULTIVARIATE_MI || (o->prune != 0 && o->prune != 1))
+    return c->fail(KSG_EINVAL, "select_parents: mode %d / prune %d not known", o->mode, o->prune);
   KSG_HIP(c, hipSetDevice(c->device));
 
   Selector s;
@@ -120,8 +122,8 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   if (st) return st;
   double* d_cmi = (double*)c->cmi.ptr;
 
-  for (int i = 0; i < s.C; ++i) s.pool.push_back(i);
   out->n = 0;
+  out->n_pruned = 0;
   out->n_steps = 0;
   out->n_fallback = 0;
   out->n_disagree = 0;
@@ -138,6 +140,12 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
     if (st) return st;
   }
 
+  // Inclusion over s.pool, conditioning on (and extending) s.selected; parents are recorded in
+  // inclusion order.
+  std::vector<int> incl;       // every included candidate, in order
+  std::vector<double> incl_t;  // t_obs and p-value of its step
+  std::vector<double> incl_p;
+  auto include_loop = [&]() -> int {
   while (!s.pool.empty() && (o->max_steps <= 0 || out->n_steps < o->max_steps)) {
     if (2 + (int)s.selected.size() > KSG_MAX_DIMS) break;  // conditioning set at the dimension limit
     const int cands = (int)s.pool.size();
@@ -195,15 +203,111 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
     out->n_steps++;
     if (decision != 1) break;
     const int chosen = s.pool[c_star];
-    if (out->n < out->capacity) {
-      if (out->var) out->var[out->n] = chosen / s.L;
-      if (out->lag) out->lag[out->n] = chosen % s.L + 1;
-      if (out->cmi) out->cmi[out->n] = t_obs;
-      if (out->pval) out->pval[out->n] = pval;
-    }
-    out->n++;
+    incl.push_back(chosen);
+    incl_t.push_back(t_obs);
+    incl_p.push_back(pval);
     s.selected.push_back(chosen);
     s.pool.erase(s.pool.begin() + c_star);
+  }
+  return KSG_OK;
+  };
+
+  const int n_vars_all = s.C / s.L;
+  if (o->mode == KSG_MODE_BIVARIATE_TE) {
+    for (int l = 0; l < s.L; ++l) s.pool.push_back(target * s.L + l);
+    st = include_loop();
+    if (st) return st;
+    const std::vector<int> tgt_sel = s.selected;
+    for (int v = 0; v < n_vars_all; ++v) {
+      if (v == target) continue;
+      s.selected = tgt_sel;
+      s.pool.clear();
+      for (int l = 0; l < s.L; ++l) s.pool.push_back(v * s.L + l);
+      st = include_loop();
+      if (st) return st;
+    }
+    // the parent set: the target past, then every source's lags
+    s.selected = incl;
+  } else {
+    for (int i = 0; i < s.C; ++i)
+      if (o->mode == KSG_MODE_MULTIVARIATE_TE || i / s.L != target) s.pool.push_back(i);
+    st = include_loop();
+    if (st) return st;
+  }
+
+  // ---- min-statistic pruning of the selected sources ----
+  std::vector<int> kept = incl;
+  std::vector<int> pruned;
+  if (o->prune) {
+    std::vector<double> h_tab;
+    for (;;) {
+      std::vector<int> src;
+      for (int cidx : kept)
+        if (cidx / s.L != target) src.push_back(cidx);
+      if (src.empty()) break;
+      std::vector<Problem> probs;
+      probs.reserve(src.size() * (s.P + 1));
+      for (size_t i = 0; i < src.size(); ++i) {
+        for (int p = 0; p <= s.P; ++p) {
+          Problem q;
+          std::memset(&q, 0, sizeof q);
+          q.n = s.N;
+          q.dx = 1;
+          q.dy = 1;
+          q.k = o->k;
+          q.col[0] = cand + (int64_t)src[i] * s.n_pad;
+          q.perm[0] = p > 0 ? o->perms + (int64_t)(p - 1) * s.N : nullptr;
+          q.padded[0] = true;
+          q.col[1] = y;
+          q.padded[1] = true;
+          int a = 2;
+          for (int other : kept)
+            if (other != src[i]) {
+              q.col[a] = cand + (int64_t)other * s.n_pad;
+              q.padded[a++] = true;
+            }
+          q.dz = a - 2;
+          q.out_index = (int)i * (s.P + 1) + p;
+          probs.push_back(q);
+        }
+      }
+      st = c->run_batch(probs, d_cmi);
+      if (st) return st;
+      out->n_cmi += (int64_t)probs.size();
+      h_tab.resize(probs.size());
+      KSG_HIP(c, hipMemcpyAsync(h_tab.data(), d_cmi, sizeof(double) * h_tab.size(), hipMemcpyDeviceToHost,
+                                c->stream));
+      KSG_HIP(c, hipStreamSynchronize(c->stream));
+      // minimum statistic: T_min over the originals (lowest index on ties), per-round minima
+      int c_min = 0;
+      for (size_t i = 1; i < src.size(); ++i)
+        if (h_tab[i * (s.P + 1)] < h_tab[(size_t)c_min * (s.P + 1)]) c_min = (int)i;
+      const double t_min = h_tab[(size_t)c_min * (s.P + 1)];
+      int count = 0;
+      for (int p = 1; p <= s.P; ++p) {
+        double m = h_tab[p];
+        for (size_t i = 1; i < src.size(); ++i) m = std::min(m, h_tab[i * (s.P + 1) + p]);
+        if (m >= t_min) ++count;
+      }
+      if ((double)count / s.P < o->alpha) break;  // significant: keep the rest
+      pruned.push_back(src[c_min]);
+      kept.erase(std::find(kept.begin(), kept.end(), src[c_min]));
+    }
+    s.selected = kept;
+  }
+  out->n_pruned = (int32_t)pruned.size();
+  for (size_t i = 0; i < pruned.size() && (int)i < out->capacity; ++i)
+    if (out->pruned) out->pruned[i] = pruned[i];
+  // parents: the kept candidates in inclusion order, with their inclusion step's statistics
+  for (size_t i = 0; i < incl.size(); ++i) {
+    if (std::find(kept.begin(), kept.end(), incl[i]) == kept.end()) continue;
+    if (out->n < out->capacity) {
+      if (out->var) out->var[out->n] = incl[i] / s.L;
+      if (out->lag) out->lag[out->n] = incl[i] % s.L + 1;
+      if (out->cmi) out->cmi[out->n] = incl_t[i];
+      if (out->pval) out->pval[out->n] = incl_p[i];
+    }
+    out->n++;
   }
 
   if (o->omnibus) {
@@ -299,5 +403,18 @@ extern "C" int ksg_greedy_step(ksg_ctx* c, const float* cand, const float* y, in
   result->pval = m.pval;
   result->tau05 = m.tau05;
   result->tau01 = m.tau01;
+  return KSG_OK;
+}
+
+extern "C" int ksg_fdr_bh(const double* pvals, int32_t n, double alpha, int32_t* reject) {
+  if (!pvals || !reject || n < 0 || !(alpha > 0 && alpha < 1)) return KSG_EINVAL;
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pvals[a] < pvals[b]; });
+  int r = 0;
+  for (int i = 0; i < n; ++i)
+    if (pvals[order[i]] <= (double)(i + 1) * alpha / n) r = i + 1;
+  for (int i = 0; i < n; ++i) reject[i] = 0;
+  for (int i = 0; i < r; ++i) reject[order[i]] = 1;
   return KSG_OK;
 }

@@ -85,3 +85,19 @@ def test_product_never_imports_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in txt.replace("the oracle", ""), f
                 assert "import workloads" not in txt, f
+
+
+def test_fdr_bh_matches_oracle():
+    """The library's Benjamini-Hochberg (host code) against the oracle's."""
+    import paper_1807_10459_amd as ksg
+    import workloads
+    from oracle.stats import fdr_bh
+    g = workloads.rng(15)
+    for _ in range(200):
+        m = int(g.integers(0, 25))
+        p = np.where(g.random(m) < 0.3, g.random(m) * 0.01, g.random(m))
+        p[g.random(m) < 0.2] = 0.02  # ties
+        alpha = float(g.choice([0.01, 0.05, 0.2]))
+        assert np.array_equal(ksg.fdr_bh(p, alpha), fdr_bh(p, alpha))
+    with pytest.raises(ksg.KsgError):
+        ksg.fdr_bh([0.1], 1.5)

@@ -127,3 +127,56 @@ def test_ar2_full_size_recovers_true_parents(lib, ctx):
     assert len(got) <= len(want) + 2  # few false positives at alpha = 0.05
     # the steps' p-values of included parents are below alpha
     assert all(p < 0.05 for p in r["pval"])
+
+
+@pytest.mark.parametrize("mode", ["bte", "mmi", "mte"])
+def test_select_parents_modes_match_oracle(lib, ctx, mode):
+    """Bivariate TE, multivariate MI and multivariate TE selections equal the oracle's step by
+    step (redundant driver copies: the modes give different parent sets)."""
+    from oracle.stats import network_select
+    data = workloads.redundant_driver_network(61)
+    L, P = 2, 19
+    cand, y = embed(data, target=3, max_lag=L)
+    perms = workloads.permutations(y.size, P, seed=62)
+    sel, steps = network_select(cand, y, 3, L, 4, perms, mode=mode)
+    r = ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=L, mode=mode)
+    assert r["candidates"] == sel
+    assert r["n_steps"] == len(steps)
+    st = [s for s in steps if s.significant]
+    for i, s in enumerate(st):
+        assert abs(r["cmi"][i] - s.t_obs) <= tol(s.t_obs)
+        assert r["pval"][i] == s.pval
+
+
+def test_select_parents_pruning_matches_oracle(lib, ctx):
+    """Min-statistic pruning after inclusion, against the oracle's (with a forced-in noise
+    source, the oracle removes it: see its pins)."""
+    from oracle.stats import greedy_select, prune_min_statistic
+    data = workloads.redundant_driver_network(63)
+    L, P = 1, 39
+    cand, y = embed(data, target=3, max_lag=L)
+    perms = workloads.permutations(y.size, P, seed=64)
+    sel, _ = greedy_select(cand, y, 4, perms)
+    kept, removed, rounds = prune_min_statistic(cand, y, sel, 3, L, 4, perms)
+    r = ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=L, prune=True, omnibus=True)
+    assert r["candidates"] == kept
+    assert r["pruned"] == removed
+    om = omnibus_test(cand, y, kept, target=3, max_lag=L, k=4, perms=perms)
+    if om is not None:
+        assert r["omnibus_tested"] and r["omnibus_pval"] == om[1].pval
+
+
+def test_select_parents_pruning_removal_matches_oracle(lib, ctx):
+    """A case in which the min-statistic test removes a source (logistic-map network, six of
+    its variables, one trial; found by searching seeds with the oracle)."""
+    from oracle.stats import greedy_select, prune_min_statistic
+    data = np.ascontiguousarray(workloads.logistic_network(seed=136, n_trials=1, T=260).data[:, :6])
+    L, P, alpha, target = 2, 19, 0.3, 1
+    cand, y = embed(data, target=target, max_lag=L)
+    perms = workloads.permutations(y.size, P, seed=137)
+    sel, _ = greedy_select(cand, y, 4, perms, alpha=alpha)
+    kept, removed, _ = prune_min_statistic(cand, y, sel, target, L, 4, perms, alpha=alpha)
+    assert removed  # the case exercises a removal
+    r = ctx.select_parents(dev(data), target=target, perms=dev(perms), k=4, max_lag=L, alpha=alpha, prune=True)
+    assert r["pruned"] == removed
+    assert r["candidates"] == [c for c in sel if c in kept]

@@ -119,16 +119,8 @@ def test_omnibus():
 
 # ---- selection modes, min-statistic pruning, FDR (readings in oracle.stats) ----
 
-def _copy_chain(seed, T=170, n_trials=2):
-    """Target 3 driven by source 0 at lag 1 with an autoregressive own past; source 1 is a
-    near-copy of source 0 (redundant given it); source 2 is noise."""
-    g = workloads.rng(seed)
-    x = g.standard_normal((n_trials, 4, T))
-    x[:, 1] = x[:, 0] + 0.05 * g.standard_normal((n_trials, T))
-    for tr in range(n_trials):
-        for t in range(1, T):
-            x[tr, 3, t] = 0.9 * x[tr, 0, t - 1] + 0.5 * x[tr, 3, t - 1] + 0.3 * g.standard_normal()
-    return x.astype(np.float32)
+def _copy_chain(seed):
+    return workloads.redundant_driver_network(seed)
 
 
 def test_selection_modes_on_redundant_sources():

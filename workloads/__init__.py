@@ -234,3 +234,27 @@ def mlp_init(seed: int, n_params: int = 5378) -> np.ndarray:
     out = np.concatenate(parts).astype(np.float32)
     assert out.size == n_params
     return out
+
+
+def redundant_driver_network(seed: int, T: int = 170, n_trials: int = 2) -> np.ndarray:
+    """[n_trials][4][T] FP32: variable 3 driven by variable 0 at lag 1 plus its own past at lag
+    1; variable 1 is a near-copy of variable 0 (redundant given it); variable 2 is noise."""
+    g = rng(seed)
+    x = g.standard_normal((n_trials, 4, T))
+    x[:, 1] = x[:, 0] + 0.05 * g.standard_normal((n_trials, T))
+    for tr in range(n_trials):
+        for t in range(1, T):
+            x[tr, 3, t] = 0.9 * x[tr, 0, t - 1] + 0.5 * x[tr, 3, t - 1] + 0.3 * g.standard_normal()
+    return x.astype(np.float32)
+
+
+def proxy_driver_network(seed: int, T: int = 200, n_trials: int = 2) -> np.ndarray:
+    """[n_trials][4][T] FP32: variable 3 driven by variables 0 and 1 at lag 1; variable 2 is a
+    noisy proxy of their sum (informative alone, redundant once both drivers are known)."""
+    g = rng(seed)
+    x = g.standard_normal((n_trials, 4, T))
+    x[:, 2] = x[:, 0] + x[:, 1] + 0.5 * g.standard_normal((n_trials, T))
+    for tr in range(n_trials):
+        for t in range(1, T):
+            x[tr, 3, t] = x[tr, 0, t - 1] + x[tr, 1, t - 1] + 0.3 * g.standard_normal()
+    return x.astype(np.float32)
