@@ -95,7 +95,7 @@ TRAIN_PLAN = ([("ar2", 1000 + i, n) for i, n in enumerate([2000] * 30 + [5000] *
 def _subsets_for(g):
     def f(n_pool, step):
         subs = [list(range(n_pool))]
-        for _ in range(47):
+        for _ in range(127):
             size = int(np.exp(g.uniform(0, np.log(n_pool))))
             subs.append(sorted(g.choice(n_pool, max(1, size), replace=False).tolist()))
         return subs
