@@ -223,6 +223,87 @@ def c4_evaluate(ctx, args, log):
     }
 
 
+# Parent set that the plain greedy selection returns for target 0 of the 20-node logistic
+# network (seed 3, 500 surrogates, k = 4): (variable, lag) pairs in inclusion order.
+OMNIBUS_PARENTS = [(0, 1), (2, 2), (15, 1), (15, 2), (0, 2), (2, 3), (2, 1), (0, 3), (2, 4), (15, 3),
+                   (2, 5), (0, 5), (6, 1), (0, 4), (9, 2)]
+
+
+def omnibus_bench(ksg, args):
+    """The omnibus test of that parent set: I(10 source columns ; Y | 5 target-past columns) and
+    500 surrogates permuting the source block's rows jointly (501 problems of 16 columns at
+    N = 29,950), one batched launch per step."""
+    import torch
+    import workloads
+    net = workloads.logistic_network(seed=3)
+    data = torch.from_numpy(net.data).cuda()
+    ctx = ksg.Context(0)
+    cand, y = ctx.embed(data, target=0, max_lag=MAX_LAG)
+    N = y.shape[0]
+    idx = [v * MAX_LAG + lag - 1 for (v, lag) in OMNIBUS_PARENTS]
+    src = [c for c in idx if c // MAX_LAG != 0]
+    tgt = [c for c in idx if c // MAX_LAG == 0]
+    xs = cand[src].contiguous()
+    zs = cand[tgt].contiguous()
+    y1 = y.reshape(1, -1).contiguous()
+    P = 500
+    perms = torch.from_numpy(workloads.permutations(N, P, seed=33)).cuda()
+    probs = [ksg.Problem(xs, y1, zs, K)] + [ksg.Problem(xs, y1, zs, K, perm_x=perms[p]) for p in range(P)]
+    for _ in range(args.warmup):
+        ctx.cmi_batch(probs)
+    torch.cuda.synchronize()
+    ctx.set_option(ctx.OPT_TIMING, 1)
+    ctx.take_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.cmi_batch(probs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.take_timing()
+    kern = ctx.last_kernels()
+    ctx.set_option(ctx.OPT_TIMING, 0)
+    ms, ops, nl = kern["single"]
+    D = len(src) + 1 + len(tgt)
+    achieved = ops / (ms * 1e-3)
+    res = out.cpu().numpy()
+    line = {
+        "metric": "CMI estimates/sec incl. surrogates (omnibus test, N=29950, k=4)",
+        "value": round((P + 1) * args.steps / wall, 1),
+        "unit": "CMI/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * wall / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (FP32 differences/compares, FP64 digamma sums)",
+        "data": "synthetic",
+        "config": {"workload": f"omnibus test of target 0's parent set, 20-node logistic network, "
+                               f"N={N}, {len(src)} source + 1 target + {len(tgt)} target-past columns "
+                               f"(D={D}), k=4, {P} surrogates"},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
+                     "peak": round(PEAK_VALU / 1e12, 3), "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_VALU, 4), "traffic": None,
+                     "kernel": KERNEL_NAMES["single"], "kernel_ms_per_launch": round(ms / nl, 3),
+                     "launches": nl, "ops_per_launch": ops / nl},
+        "omnibus_cmi": float(res[0]),
+        "omnibus_pval": float(np.mean(res[1:] >= res[0])),
+    }
+    if not args.no_cpu_baseline:
+        from oracle.ksg import ksg_cmi
+        xs_np, y_np, zs_np = xs.cpu().numpy().T, y.cpu().numpy(), zs.cpu().numpy().T
+        t1 = time.perf_counter()
+        ref = ksg_cmi(xs_np, y_np, zs_np, K)
+        dt = time.perf_counter() - t1
+        line["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "CMI/s", "cores": 1, "kind": "oracle",
+                                "sample": "the original (unpermuted) omnibus CMI, one process"}
+        line["parity_spot_check_abs_err"] = abs(float(res[0]) - ref)
+    ctx.close()
+    return line
+
+
 TRAFFIC_SOURCES = ("ksg_group.inc.h", "ksg_search.inc.h", "ksg_yzcount.hip")
 KERNEL_NAMES = {"radius": "ksg_group_radius_kernel (k-NN radius of each problem of a group, "
                           "Y/Z distances shared, key-ordered windows)",
@@ -259,7 +340,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--group-size", type=int, default=-1,
                     help="problems searched together (-1 tuned, 0 off, 8, 16)")
-    ap.add_argument("--workload", default="ar2", choices=["ar2", "c4", "modes"],
+    ap.add_argument("--workload", default="ar2", choices=["ar2", "c4", "modes", "omnibus"],
                     help="ar2: CMI/s on the AR(2) forced path (default); c4: learned vs plain null")
     ap.add_argument("--targets", default=None, help="c4: comma-separated targets (default all 20)")
     ap.add_argument("--dataset", default=None, help="c4: load the training set from this npz")
@@ -321,6 +402,11 @@ def main():
                   file=sys.stderr, flush=True)
         print(json.dumps({"workload": "selection variants, AR(2) 5-node network, target 0, N=10000, "
                                       "k=4, 200 surrogates", "true_source_vars": true_src, "runs": out}))
+        return
+
+    if args.workload == "omnibus":
+        line = omnibus_bench(ksg, args)
+        print(json.dumps(line))
         return
 
     if args.dump_dataset:

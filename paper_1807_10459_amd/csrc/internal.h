@@ -117,7 +117,9 @@ struct MaxStatOut {
 
 // ---- launchers implemented in the .hip translation units ----
 // Search + count + per-tile digamma partial sums for every work item, then the
-// per-problem finalisation.  kp = number of top-k registers (5, 9 or 17).
+// per-problem finalisation.  kp = number of top-k registers (5, 9 or 17); shape = the common
+// fast shape id of the launch, kGenericShape + D when every problem is a generic shape of D
+// columns, or -1 for a mixed launch.
 hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                              const double* d_htab, double* d_partials, int shape, int kp,
                              hipStream_t stream);

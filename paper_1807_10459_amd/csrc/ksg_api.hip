@@ -484,11 +484,12 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       d.part_base = part;
       part += d.n_tiles;
       kp = std::max(kp, p.k + 1 <= 5 ? 5 : (p.k + 1 <= 9 ? 9 : 17));
-      if (common_shape == -2) common_shape = d.variant;
-      else if (common_shape != d.variant) common_shape = -1;
+      // generic shapes share a kernel when their column counts agree
+      const int launch_shape = d.variant >= kGenericShape ? kGenericShape + D : d.variant;
+      if (common_shape == -2) common_shape = launch_shape;
+      else if (common_shape != launch_shape) common_shape = -1;
     }
   }
-  if (common_shape >= kGenericShape) common_shape = -1;
 
   // ungrouped work items
   std::vector<Unit> units;

@@ -13,9 +13,9 @@
 
 namespace ksg {
 
-extern const void* search_kernels_kp5[40];
-extern const void* search_kernels_kp9[40];
-extern const void* search_kernels_kp17[40];
+extern const void* search_kernels_kp5[55];
+extern const void* search_kernels_kp9[55];
+extern const void* search_kernels_kp17[55];
 extern const void* group_radius_kernels_kp5_g8[15];
 extern const void* group_radius_kernels_kp5_g16[15];
 extern const void* group_radius_kernels_kp9_g8[15];
@@ -260,6 +260,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const ProbDesc* __restric
 static const void* pick_search_kernel(int shape, int kp) {
   const void* const* table = kp <= 5 ? search_kernels_kp5 : (kp <= 9 ? search_kernels_kp9 : search_kernels_kp17);
   if (shape >= 0 && shape < 39) return table[shape];
+  if (shape >= kGenericShape + 2 && shape <= kGenericShape + kMaxDims) return table[40 + shape - kGenericShape - 2];
   return table[39];
 }
 

@@ -110,29 +110,9 @@ __device__ __forceinline__ void tile_epilogue(const KSG_AS4 ProbDesc* pd, int ti
   if (threadIdx.x == 0) partials[pd->part_base + tile] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
 }
 
-// Fast path: compile-time subspace dimensions.
-template <int DX, int DY, int DZ, int KP, int U>
-__device__ __forceinline__ void search_tile(const KSG_AS4 ProbDesc* pd, int tile,
-                                            const double* __restrict__ htab,
-                                            double* __restrict__ partials, double* s_red) {
-  constexpr int D = DX + DY + DZ;
-  const int n = pd->n;
-  const int n_pad = pd->n_pad;
-  const int k = pd->k;
-  const int qraw = tile * kTileQ + (int)threadIdx.x;
-  const bool valid = qraw < n;
-  const int qi = valid ? qraw : n - 1;
-
-  cfptr col[D];
-  float q[D];
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const float* c = pd->col[a];
-    col[a] = (cfptr)c;
-    q[a] = c[qi];
-  }
-
-  // ---- pass 1: the (k+1) smallest joint distances, self included ----
+// Pass 1: the (k+1) smallest joint distances, self included; returns eps_i.
+template <int D, int KP, int U>
+__device__ __forceinline__ float radius_pass(const cfptr (&col)[D], const float (&q)[D], int n_pad, int k) {
   float b[KP];
 #pragma unroll
   for (int i = 0; i < KP; ++i) b[i] = (i < KP - 1 - k) ? -INFINITY : INFINITY;
@@ -154,10 +134,20 @@ __device__ __forceinline__ void search_tile(const KSG_AS4 ProbDesc* pd, int tile
       for (int u = 0; u < U; ++u) topk_insert<KP>(b, d[u]);
     }
   }
-  const float eps = b[KP - 1];
+  return b[KP - 1];
+}
 
-  // ---- pass 2: strict counts in XZ, YZ and Z (self included, removed in the epilogue) ----
-  // One accumulator per unrolled reference keeps every count a compare + add-with-carry.
+// Pass 2: strict counts in XZ, YZ and Z (self included, removed in the epilogue), for a
+// compile-time split of the D = DX + DY + DZ columns.  One accumulator per unrolled reference
+// keeps every count a compare + add-with-carry.
+struct Counts {
+  int xz, yz, z;
+};
+
+template <int DX, int DY, int DZ, int U>
+__device__ __forceinline__ Counts count_pass(const cfptr (&col)[DX + DY + DZ], const float (&q)[DX + DY + DZ],
+                                             int n_pad, float eps) {
+  constexpr int D = DX + DY + DZ;
   unsigned axz[U], ayz[U], az[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) axz[u] = ayz[u] = az[u] = 0u;
@@ -183,14 +173,108 @@ __device__ __forceinline__ void search_tile(const KSG_AS4 ProbDesc* pd, int tile
       }
     }
   }
-  int cxz = 0, cyz = 0, cz = 0;
+  Counts c{0, 0, 0};
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    cxz += (int)axz[u];
-    cyz += (int)ayz[u];
-    cz += (int)az[u];
+    c.xz += (int)axz[u];
+    c.yz += (int)ayz[u];
+    c.z += (int)az[u];
   }
-  tile_epilogue(pd, tile, qi, valid, eps, cxz, cyz, cz, DZ == 0, htab, partials, s_red);
+  return c;
+}
+
+// Pass 2 for a split known only at run time: subspace membership per column by selects.
+template <int D>
+__device__ __forceinline__ Counts count_pass_split(const cfptr (&col)[D], const float (&q)[D], int n_pad,
+                                                   float eps, int dx, int dy) {
+  constexpr int U = 4;
+  int cxz = 0, cyz = 0, cz = 0;
+  for (int j = 0; j < n_pad; j += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float A = 0.0f, B = 0.0f, C = 0.0f;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const float t = fabsf(col[a][j + u] - q[a]);
+        if (a < dx) A = fmaxf(A, t);
+        else if (a < dx + dy) B = fmaxf(B, t);
+        else C = fmaxf(C, t);
+      }
+      cxz += fmaxf(A, C) < eps;
+      cyz += fmaxf(B, C) < eps;
+      cz += C < eps;
+    }
+  }
+  return Counts{cxz, cyz, cz};
+}
+
+// Pass 2 for dx == 1 and a wave-uniform dy in [DY, D): one compile-time count loop per dy,
+// selected once per tile, so the reference loop carries no per-column selects.
+template <int D, int DY, int U>
+__device__ __forceinline__ Counts count_pass_dx1(const cfptr (&col)[D], const float (&q)[D], int n_pad,
+                                                 float eps, int dy) {
+  if constexpr (DY < D - 1) {
+    if (dy == DY) return count_pass<1, DY, D - 1 - DY, U>(col, q, n_pad, eps);
+    return count_pass_dx1<D, DY + 1, U>(col, q, n_pad, eps, dy);
+  } else {
+    return count_pass<1, D - 1, 0, U>(col, q, n_pad, eps);  // dy == D - 1: no Z
+  }
+}
+
+// Fast path: compile-time subspace dimensions.
+template <int DX, int DY, int DZ, int KP, int U>
+__device__ __forceinline__ void search_tile(const KSG_AS4 ProbDesc* pd, int tile,
+                                            const double* __restrict__ htab,
+                                            double* __restrict__ partials, double* s_red) {
+  constexpr int D = DX + DY + DZ;
+  const int n = pd->n;
+  const int n_pad = pd->n_pad;
+  const int k = pd->k;
+  const int qraw = tile * kTileQ + (int)threadIdx.x;
+  const bool valid = qraw < n;
+  const int qi = valid ? qraw : n - 1;
+
+  cfptr col[D];
+  float q[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float* c = pd->col[a];
+    col[a] = (cfptr)c;
+    q[a] = c[qi];
+  }
+  const float eps = radius_pass<D, KP, U>(col, q, n_pad, k);
+  const Counts c = count_pass<DX, DY, DZ, U>(col, q, n_pad, eps);
+  tile_epilogue(pd, tile, qi, valid, eps, c.xz, c.yz, c.z, DZ == 0, htab, partials, s_red);
+}
+
+// Dimension-count path: D columns with the split known at run time.  The canonical split has
+// dx <= dy, so dx == 1 (the usual case: one target variable against several sources, or one
+// source against several conditioning columns) gets compile-time count loops; any other split
+// counts with per-column selects.
+template <int D, int KP>
+__device__ __forceinline__ void search_tile_dims(const KSG_AS4 ProbDesc* pd, int tile,
+                                                 const double* __restrict__ htab,
+                                                 double* __restrict__ partials, double* s_red) {
+  constexpr int U = D <= 8 ? 8 : 4;
+  const int n = pd->n;
+  const int n_pad = pd->n_pad;
+  const int k = pd->k;
+  const int dx = pd->dx, dy = pd->dy;
+  const int qraw = tile * kTileQ + (int)threadIdx.x;
+  const bool valid = qraw < n;
+  const int qi = valid ? qraw : n - 1;
+  cfptr col[D];
+  float q[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const float* c = pd->col[a];
+    col[a] = (cfptr)c;
+    q[a] = c[qi];
+  }
+  const float eps = radius_pass<D, KP, U>(col, q, n_pad, k);
+  const Counts c = dx == 1 ? count_pass_dx1<D, 1, U>(col, q, n_pad, eps, dy)
+                           : count_pass_split<D>(col, q, n_pad, eps, dx, dy);
+  tile_epilogue(pd, tile, qi, valid, eps, c.xz, c.yz, c.z, dx + dy == D, htab, partials, s_red);
 }
 
 // Generic path: any split of up to kMaxDims dimensions, subspace membership resolved
@@ -216,45 +300,10 @@ __device__ __forceinline__ void search_tile_generic(const KSG_AS4 ProbDesc* pd, 
     col[a] = (cfptr)c;
     q[a] = c[qi];
   }
-  float b[KP];
-#pragma unroll
-  for (int i = 0; i < KP; ++i) b[i] = (i < KP - 1 - k) ? -INFINITY : INFINITY;
-  for (int j = 0; j < n_pad; j += U) {
-    float d[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) d[u] = fabsf(col[0][j + u] - q[0]);
-#pragma unroll
-    for (int a = 1; a < D; ++a) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) d[u] = fmaxf(d[u], fabsf(col[a][j + u] - q[a]));
-    }
-    bool hit = false;
-#pragma unroll
-    for (int u = 0; u < U; ++u) hit |= d[u] < b[KP - 1];
-    if (hit) {
-#pragma unroll
-      for (int u = 0; u < U; ++u) topk_insert<KP>(b, d[u]);
-    }
-  }
-  const float eps = b[KP - 1];
+  const float eps = radius_pass<D, KP, U>(col, q, n_pad, k);
   const bool z_empty = (dx + dy == D);
-  int cxz = 0, cyz = 0, cz = 0;
-  for (int j = 0; j < n_pad; j += U) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      float A = 0.0f, B = 0.0f, C = 0.0f;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const float t = fabsf(col[a][j + u] - q[a]);
-        if (a < dx) A = fmaxf(A, t);
-        else if (a < dx + dy) B = fmaxf(B, t);
-        else C = fmaxf(C, t);
-      }
-      cxz += fmaxf(A, C) < eps;
-      cyz += fmaxf(B, C) < eps;
-      cz += C < eps;
-    }
-  }
+  const Counts c = count_pass_split<D>(col, q, n_pad, eps, dx, dy);
+  const int cxz = c.xz, cyz = c.yz, cz = c.z;
   tile_epilogue(pd, tile, qi, valid, eps, cxz, cyz, cz, z_empty, htab, partials, s_red);
 }
 
@@ -300,8 +349,9 @@ __device__ __forceinline__ void dispatch_generic(int D, const KSG_AS4 ProbDesc* 
 // Batched kernel: one work-group per work item (problem, 256-query tile).  The host orders
 // the items longest-problem-first and the hardware dispatcher hands work-groups to compute
 // units in that order as they free up, which gives the dynamic longest-first schedule of a
-// work queue without a device-side queue.  SHAPE >= 0: every problem of the launch has that
-// fast shape; SHAPE == -1: mixed batch, per-problem dispatch.
+// work queue without a device-side queue.  SHAPE in [0, kGenericShape): every problem of the
+// launch has that fast shape; SHAPE == kGenericShape + D: every problem is a generic shape of D
+// columns; SHAPE == -1: mixed batch, per-problem dispatch.
 template <int SHAPE, int KP>
 __global__ __launch_bounds__(kTileQ) void ksg_batch_kernel(const ProbDesc* __restrict__ descs,
                                                            const WorkItem* __restrict__ items,
@@ -315,7 +365,9 @@ __global__ __launch_bounds__(kTileQ) void ksg_batch_kernel(const ProbDesc* __res
   if (prob < 0) return;
   const int tile = i4[it].tile;
   const KSG_AS4 ProbDesc* pd = d4 + prob;
-  if constexpr (SHAPE >= 0 && SHAPE < kGenericShape) {
+  if constexpr (SHAPE >= kGenericShape + 2) {
+    search_tile_dims<SHAPE - kGenericShape, KP>(pd, tile, htab, partials, s_red);
+  } else if constexpr (SHAPE >= 0 && SHAPE < kGenericShape) {
     constexpr int PAIR = SHAPE / (kFastMaxDz + 1);
     constexpr int DZ = SHAPE % (kFastMaxDz + 1);
     constexpr int DX = PAIR == 2 ? 2 : 1;

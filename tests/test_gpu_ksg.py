@@ -118,6 +118,33 @@ def test_denormals_and_large_magnitudes(lib, ctx):
     _check_full(lib, ctx, x, y, z, 4, "denormal")
 
 
+@pytest.mark.parametrize("dims_list", [
+    [(3, 1, 2), (1, 3, 2), (1, 4, 1), (2, 3, 1), (1, 5, 0), (4, 2, 0)],  # D = 6
+    [(4, 1, 4), (1, 6, 2), (3, 3, 3), (1, 8, 0), (2, 2, 5)],              # D = 9; (2, 2, 5) fast
+])
+def test_generic_same_width_batch(lib, ctx, dims_list):
+    """Generic shapes of one column count share one launch (per-width kernel, compile-time
+    count loops for a one-column X and selects otherwise); counts exact on every point."""
+    import torch
+    probs, outs, data = [], [], []
+    for i, dims in enumerate(dims_list):
+        n = 600 + 97 * i
+        pr = workloads.random_problem(1000 + i, n, *dims, 3)
+        eps = torch.empty(n, dtype=torch.float32, device="cuda")
+        cnt = torch.empty((3, n), dtype=torch.int32, device="cuda")
+        probs.append(lib.Problem(soa(pr.x), soa(pr.y), soa(pr.z), 3, eps_out=eps, counts_out=cnt))
+        outs.append((eps, cnt))
+        data.append(pr)
+    res = ctx.cmi_batch(probs).cpu().numpy()
+    for i, pr in enumerate(data):
+        e, a, b, c = ksg_counts(pr.x, pr.y, pr.z, 3)
+        cnt = outs[i][1].cpu().numpy()
+        assert np.array_equal(outs[i][0].cpu().numpy(), e), dims_list[i]
+        assert np.array_equal(cnt[0], a) and np.array_equal(cnt[1], b) and np.array_equal(cnt[2], c), dims_list[i]
+        ref = ksg_cmi_from_counts(pr.n, 3, a, b, c)
+        assert abs(res[i] - ref) <= tol(ref), dims_list[i]
+
+
 def test_surrogate_gather(lib, ctx):
     p, perms, _ = workloads.gaussian_trivariate(seed=0, n_perm=3)
     for q in range(3):
