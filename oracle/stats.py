@@ -39,7 +39,15 @@ taken here (network_select, min_statistic, prune_min_statistic, fdr_bh):
   if p >= alpha the minimising source is removed and the test repeats,
   otherwise every remaining source is kept;
 * FDR across targets: Benjamini-Hochberg at level alpha on the targets'
-  omnibus p-values.
+  omnibus p-values;
+* sequential max-statistic final test of the selected sources: every
+  selected source c gets I(c ; Y | every other selected candidate) and its
+  surrogates (as for pruning); the observed values are ranked in descending
+  order (lowest index first on ties) and the r-th largest is compared with
+  the distribution over rounds of the r-th largest surrogate value of that
+  round: p_r = #{p : T_p,(r) >= I_(r)} / P; ranks are tested from r = 1 and
+  the first rank with p_r >= alpha ends the test: that source and every
+  later-ranked one are removed, the earlier ones are kept.
 """
 from __future__ import annotations
 
@@ -62,6 +70,8 @@ __all__ = [
     "min_statistic",
     "prune_min_statistic",
     "fdr_bh",
+    "max_statistic_sequential",
+    "sequential_final_test",
 ]
 
 MAX_COND = 14  # conditioning columns: 16 dimensions with X and Y
@@ -279,3 +289,48 @@ def fdr_bh(pvals, alpha: float = 0.05) -> np.ndarray:
     out = np.zeros(m, dtype=bool)
     out[order[:r]] = True
     return out
+
+
+def max_statistic_sequential(cmi: np.ndarray, alpha: float = 0.05):
+    """cmi: FP64 [c][P+1] (column 0 originals).  Returns (significant bool [c], pval [c]) in the
+    row order; ranks after the first non-significant one keep p = 1 and are not significant."""
+    cmi = np.asarray(cmi, dtype=np.float64)
+    orig = cmi[:, 0]
+    n, P = orig.size, cmi.shape[1] - 1
+    rank_order = sorted(range(n), key=lambda c: (-orig[c], c))  # descending, lowest index on ties
+    surr_sorted = -np.sort(-cmi[:, 1:], axis=0)                  # every round descending
+    sig = np.zeros(n, dtype=bool)
+    pval = np.ones(n)
+    for r, c in enumerate(rank_order):
+        count = int(np.sum(surr_sorted[r, :] >= orig[c]))
+        pval[c] = count / P
+        if pval[c] >= alpha:
+            break
+        sig[c] = True
+    return sig, pval
+
+
+def sequential_final_test(cand, y, selected, target: int, max_lag: int, k: int, perms,
+                          alpha: float = 0.05):
+    """Sequential max-statistic test of the selected sources.  Returns (kept selection in the
+    original order, removed sources in rank order, {source: p-value} of every tested source,
+    the [n_src][P+1] table)."""
+    cand = np.asarray(cand, dtype=np.float32)
+    y = np.asarray(y, dtype=np.float32)
+    perms = np.asarray(perms)
+    src = [c for c in selected if c // max_lag != target]
+    if not src:
+        return list(selected), [], {}, np.zeros((0, perms.shape[0] + 1))
+    P = perms.shape[0]
+    table = np.empty((len(src), P + 1))
+    for i, c in enumerate(src):
+        others = [cand[o] for o in selected if o != c]
+        z = np.stack(others, axis=1) if others else np.zeros((y.size, 0), np.float32)
+        table[i, 0] = ksg_cmi(cand[c], y, z, k)
+        for p in range(P):
+            table[i, p + 1] = ksg_cmi(cand[c][perms[p]], y, z, k)
+    sig, pval = max_statistic_sequential(table, alpha)
+    order = sorted(range(len(src)), key=lambda i: (-table[i, 0], i))
+    removed = [src[i] for i in order if not sig[i]]
+    kept = [c for c in selected if c not in removed]
+    return kept, removed, {src[i]: float(pval[i]) for i in range(len(src))}, table

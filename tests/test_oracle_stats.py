@@ -196,3 +196,68 @@ def test_fdr_bh_matches_library():
         ref = false_discovery_control(p, method="bh") <= alpha
         assert np.array_equal(fdr_bh(p, alpha), ref)
     assert fdr_bh([0.01, 0.04, 0.03, 0.2], 0.05).tolist() == [True, False, False, False]
+
+
+def test_sequential_max_statistic_hand_example():
+    from oracle.stats import max_statistic_sequential
+    # originals 0.2, 0.9, 0.5 -> ranks: row 1 (0.9), row 2 (0.5), row 0 (0.2).
+    # rounds (columns) sorted descending: round 1 (0.3, 0.1, 0.4) -> 0.4, 0.3, 0.1;
+    # round 2 (0.6, 0.2, 0.1) -> 0.6, 0.2, 0.1.
+    # rank 1: 0.9 vs {0.4, 0.6} -> p = 0; rank 2: 0.5 vs {0.3, 0.2} -> p = 0;
+    # rank 3: 0.2 vs {0.1, 0.1} -> p = 0: all significant at any alpha > 0.
+    t = np.array([[0.2, 0.3, 0.6], [0.9, 0.1, 0.2], [0.5, 0.4, 0.1]])
+    sig, p = max_statistic_sequential(t, 0.05)
+    assert sig.tolist() == [True, True, True] and p.tolist() == [0.0, 0.0, 0.0]
+    # raise row 0's surrogate in round 2 to 0.65: sorted round 2 -> 0.65, 0.2, 0.1; still
+    # rank 1: 0.9 > 0.65 (p 0); rank 2: 0.5 vs {0.3, 0.2} (p 0); rank 3: 0.2 vs {0.1, 0.1} (p 0)
+    t[0, 2] = 0.65
+    assert max_statistic_sequential(t, 0.05)[0].all()
+    # now row 2's original drops to 0.25: ranks 1 (0.9), 2 (row 2, 0.25), 3 (row 0, 0.2);
+    # rank 2: 0.25 vs {0.3, 0.2} -> p = 1/2 >= alpha: rows 2 and 0 removed, p of row 0 stays 1
+    t[2, 0] = 0.25
+    sig, p = max_statistic_sequential(t, 0.05)
+    assert sig.tolist() == [False, True, False] and p.tolist() == [1.0, 0.0, 0.5]
+    # ties in the originals rank the lower index first
+    t2 = np.array([[0.5, 0.6, 0.0], [0.5, 0.0, 0.0]])
+    sig2, p2 = max_statistic_sequential(t2, 0.6)
+    # rank 1: row 0, 0.5 vs round maxima {0.6, 0.0} -> p = 1/2 < 0.6;
+    # rank 2: row 1, 0.5 vs second largest {0.0, 0.0} -> p = 0
+    assert sig2.tolist() == [True, True] and p2.tolist() == [0.5, 0.0]
+
+
+def test_sequential_rank_one_is_the_max_statistic_and_counting_form():
+    """Rank 1 compares the largest original with the round maxima: the max-statistic test.
+    Every rank also has a counting form: the r-th largest value of a round is >= x exactly
+    when at least r values of that round are >= x."""
+    from oracle.stats import max_statistic_sequential
+    g = workloads.rng(15)
+    for _ in range(300):
+        c = int(g.integers(1, 7))
+        P = int(g.integers(1, 30))
+        t = np.round(g.standard_normal((c, P + 1)), 1)  # coarse values: many ties
+        alpha = float(g.choice([0.05, 0.2, 0.5]))
+        sig, p = max_statistic_sequential(t, alpha)
+        ms = max_statistic(t, alpha)
+        top = max(range(c), key=lambda i: (t[i, 0], -i))
+        assert top == ms.c_star and p[top] == ms.pval and sig[top] == ms.significant
+        ranked = sorted(range(c), key=lambda i: (-t[i, 0], i))
+        stopped = False
+        for r, i in enumerate(ranked, start=1):
+            if stopped:
+                assert not sig[i] and p[i] == 1.0
+                continue
+            count = sum(1 for q in range(1, P + 1) if np.sum(t[:, q] >= t[i, 0]) >= r)
+            assert p[i] == count / P
+            assert sig[i] == (count / P < alpha)
+            stopped = not sig[i]
+
+
+def test_sequential_final_test_removes_a_noise_source():
+    from oracle.stats import sequential_final_test
+    data = _copy_chain(12)
+    L = 1
+    cand, y = embed(data, target=3, max_lag=L)
+    perms = workloads.permutations(y.size, 39, seed=13)
+    kept, removed, pv, table = sequential_final_test(cand, y, [3, 0, 2], 3, L, 4, perms)
+    assert removed == [2] and kept == [3, 0]
+    assert pv[0] < 0.05 and pv[2] >= 0.05 and table.shape == (2, 40)
