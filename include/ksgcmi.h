@@ -286,6 +286,8 @@ typedef struct ksg_select_opts {
   int32_t max_steps; /* 0 = until the test stops or the pool is empty */
   int32_t mode;      /* KSG_MODE_* */
   int32_t prune;     /* 1: min-statistic pruning of the selected sources */
+  int32_t sequential; /* 1: sequential max-statistic test of the kept sources (after pruning;
+                       * skipped when the omnibus test ran and was not significant) */
 } ksg_select_opts;
 
 enum { KSG_MODE_MULTIVARIATE_TE = 0, KSG_MODE_BIVARIATE_TE = 1, KSG_MODE_MULTIVARIATE_MI = 2 };
@@ -320,6 +322,13 @@ typedef struct ksg_parent_set {
    * entries or NULL) and how many; var/lag/cmi/pval above hold the kept parents. */
   int32_t n_pruned;
   int32_t* pruned;
+  /* Sequential test: sources removed (candidate indices in rank order; host array of capacity
+   * entries or NULL) and how many; seq_pval (host [capacity] or NULL): the test's p-value of
+   * each kept parent in the order of var/lag (-1 for the target's own past or when the test did
+   * not run). */
+  int32_t n_seq_removed;
+  int32_t* seq_removed;
+  double* seq_pval;
 } ksg_parent_set;
 
 /* data: device FP32 [n_trials][n_vars][T].  out: host struct.
@@ -333,6 +342,18 @@ int select_parents(ksg_ctx* ctx, const float* data, int32_t n_vars, int64_t T, i
  * p-values, r the largest rank with p_(r) <= r * alpha / n (ties in index order), else 0.
  * Host arrays of n entries.  Errors: KSG_EINVAL (null pointers, n < 0, alpha outside (0,1)). */
 int ksg_fdr_bh(const double* pvals, int32_t n, double alpha, int32_t* reject);
+
+/* Sequential max-statistic test (reading of the post-selection statistics named in the
+ * network-inference paragraph): table host FP64 [rows][n_perm+1], column 0 the observed CMI of
+ * each tested variable, column 1+p its surrogate of round p.  The observed values are ranked in
+ * descending order (lower row first on ties); the r-th ranked one gets p_r = #{p : r-th largest
+ * surrogate value of round p >= its value} / n_perm and is significant when p_r < alpha; the
+ * first rank that is not significant ends the test (it and every later rank: significant = 0,
+ * later ranks keep pval = 1).  Outputs host int32 significant[rows], FP64 pval[rows] in row
+ * order.  Host code, no device work.  Errors: KSG_EINVAL (null pointers, rows < 0, n_perm < 1,
+ * alpha outside (0,1)). */
+int ksg_maxstat_sequential(const double* table, int32_t rows, int32_t n_perm, double alpha,
+                           int32_t* significant, double* pval);
 
 /* ---------------------------------------------------------------------------
  * Learned null: a 16-64-64-2 perceptron (ReLU hidden layers, BF16 parameters,

@@ -16,6 +16,7 @@ from ._binding import (  # noqa: F401
     Problem,
     ThresholdNet,
     fdr_bh,
+    maxstat_sequential,
     harmonic_table,
     lib,
     lib_path,

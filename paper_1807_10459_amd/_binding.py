@@ -44,7 +44,8 @@ class _SelectOpts(C.Structure):
     _fields_ = [("k", C.c_int32), ("max_lag", C.c_int32), ("n_perm", C.c_int32),
                 ("omnibus", C.c_int32), ("alpha", C.c_double), ("perms", C.c_void_p),
                 ("learned", C.c_void_p), ("margin_lo", C.c_double), ("margin_hi", C.c_double),
-                ("judge", C.c_int32), ("max_steps", C.c_int32), ("mode", C.c_int32), ("prune", C.c_int32)]
+                ("judge", C.c_int32), ("max_steps", C.c_int32), ("mode", C.c_int32), ("prune", C.c_int32),
+                ("sequential", C.c_int32)]
 
 
 class _ParentSet(C.Structure):
@@ -55,7 +56,8 @@ class _ParentSet(C.Structure):
                 ("omnibus_cmi", C.c_double), ("omnibus_pval", C.c_double), ("n_cmi", C.c_int64),
                 ("step_capacity", C.c_int32), ("step_tobs", C.c_void_p), ("step_pred", C.c_void_p),
                 ("step_verdict", C.c_void_p), ("step_plain", C.c_void_p), ("n_pruned", C.c_int32),
-                ("pruned", C.c_void_p)]
+                ("pruned", C.c_void_p), ("n_seq_removed", C.c_int32), ("seq_removed", C.c_void_p),
+                ("seq_pval", C.c_void_p)]
 
 
 def _load():
@@ -103,6 +105,7 @@ def _load():
                                 C.POINTER(i64)], i32),
         "ksg_step_features": ([vp, vp, i32, vp, vp, i64, vp, i32, i32, i32, i32, i32, vp], i32),
         "ksg_fdr_bh": ([vp, i32, d, vp], i32),
+        "ksg_maxstat_sequential": ([vp, i32, i32, d, vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -134,6 +137,21 @@ def fdr_bh(pvals, alpha: float = 0.05) -> np.ndarray:
     if st:
         raise KsgError(st, "ksg_fdr_bh")
     return out.astype(bool)
+
+
+def maxstat_sequential(table, alpha: float = 0.05):
+    """Sequential max-statistic test of a host table [rows][P+1] (see ksg_maxstat_sequential);
+    returns (significant bool [rows], pval [rows])."""
+    t = np.ascontiguousarray(np.asarray(table, dtype=np.float64))
+    if t.ndim != 2 or t.shape[1] < 2:
+        raise ValueError("table must be [rows][n_perm + 1] with n_perm >= 1")
+    sig = np.zeros(t.shape[0], np.int32)
+    pv = np.zeros(t.shape[0], np.float64)
+    st = lib.ksg_maxstat_sequential(t.ctypes.data, t.shape[0], t.shape[1] - 1, float(alpha),
+                                    sig.ctypes.data, pv.ctypes.data)
+    if st:
+        raise KsgError(st, "ksg_maxstat_sequential")
+    return sig.astype(bool), pv
 
 
 MODES = {"mte": 0, "bte": 1, "mmi": 2}
@@ -326,16 +344,18 @@ class Context:
                        alpha: float = 0.05, omnibus: bool = False, learned: "ThresholdNet" = None,
                        margin_lo: float = 1.0, margin_hi: float = 1.0, judge: bool = False,
                        max_steps: int = 0, capacity: int = 64, mode: str = "mte",
-                       prune: bool = False) -> dict:
+                       prune: bool = False, sequential: bool = False) -> dict:
         """Parents of one target.  mode: "mte" (multivariate TE), "bte" (bivariate TE) or "mmi"
-        (multivariate MI); prune: min-statistic pruning of the selected sources."""
+        (multivariate MI); prune: min-statistic pruning of the selected sources; sequential:
+        sequential max-statistic test of the kept sources."""
         import torch
         _check_dtype(data, torch.float32, "data")
         _check_dtype(perms, torch.int32, "perms")
         n_trials, n_vars, T = data.shape
         opts = _SelectOpts(int(k), int(max_lag), int(perms.shape[0]), int(bool(omnibus)), float(alpha),
                            _ptr(perms), learned._h if learned is not None else None, float(margin_lo),
-                           float(margin_hi), int(bool(judge)), int(max_steps), MODES[mode], int(bool(prune)))
+                           float(margin_hi), int(bool(judge)), int(max_steps), MODES[mode], int(bool(prune)),
+                           int(bool(sequential)))
         var = np.zeros(capacity, np.int32)
         lag = np.zeros(capacity, np.int32)
         cmi = np.zeros(capacity, np.float64)
@@ -351,6 +371,9 @@ class Context:
         ps.step_verdict, ps.step_plain = s_v.ctypes.data, s_pl.ctypes.data
         prn = np.zeros(capacity, np.int32)
         ps.pruned = prn.ctypes.data
+        srm = np.zeros(capacity, np.int32)
+        spv = np.zeros(capacity, np.float64)
+        ps.seq_removed, ps.seq_pval = srm.ctypes.data, spv.ctypes.data
         self._check(lib.select_parents(self._h, _ptr(data), n_vars, T, n_trials, int(target),
                                        C.byref(opts), C.byref(ps)), "select_parents")
         n = ps.n
@@ -362,6 +385,8 @@ class Context:
                     omnibus_significant=bool(ps.omnibus_significant), omnibus_cmi=ps.omnibus_cmi,
                     omnibus_pval=ps.omnibus_pval, n_cmi=ps.n_cmi,
                     pruned=[int(v) for v in prn[:min(ps.n_pruned, capacity)]],
+                    seq_removed=[int(v) for v in srm[:min(ps.n_seq_removed, capacity)]],
+                    seq_pval=spv[:n].tolist(),
                     steps=[dict(t_obs=float(s_t[i]), pred=[float(s_p[i, 0]), float(s_p[i, 1])],
                                 verdict=int(s_v[i]), plain=int(s_pl[i]))
                            for i in range(min(ps.n_steps, scap))])

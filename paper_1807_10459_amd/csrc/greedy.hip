@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "../../include/ksgcmi.h"
@@ -78,8 +79,10 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   if (out->capacity < 0) return c->fail(KSG_EINVAL, "select_parents: negative capacity");
   if (o->learned && !(o->margin_lo >= 0 && o->margin_hi >= 0))
     return c->fail(KSG_EINVAL, "select_parents: margins must be >= 0");
-  if (o->mode < KSG_MODE_MULTIVARIATE_TE || o->mode > KSG_MODE_MULTIVARIATE_MI || (o->prune != 0 && o->prune != 1))
-    return c->fail(KSG_EINVAL, "select_parents: mode %d / prune %d not known", o->mode, o->prune);
+  if (o->mode < KSG_MODE_MULTIVARIATE_TE || o->mode > KSG_MODE_MULTIVARIATE_MI || (o->prune != 0 && o->prune != 1) ||
+      (o->sequential != 0 && o->sequential != 1))
+    return c->fail(KSG_EINVAL, "select_parents: mode %d / prune %d / sequential %d not known", o->mode, o->prune,
+                   o->sequential);
   KSG_HIP(c, hipSetDevice(c->device));
 
   Selector s;
@@ -238,46 +241,57 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   // ---- min-statistic pruning of the selected sources ----
   std::vector<int> kept = incl;
   std::vector<int> pruned;
-  if (o->prune) {
-    std::vector<double> h_tab;
-    for (;;) {
-      std::vector<int> src;
-      for (int cidx : kept)
-        if (cidx / s.L != target) src.push_back(cidx);
-      if (src.empty()) break;
-      std::vector<Problem> probs;
-      probs.reserve(src.size() * (s.P + 1));
-      for (size_t i = 0; i < src.size(); ++i) {
-        for (int p = 0; p <= s.P; ++p) {
-          Problem q;
-          std::memset(&q, 0, sizeof q);
-          q.n = s.N;
-          q.dx = 1;
-          q.dy = 1;
-          q.k = o->k;
-          q.col[0] = cand + (int64_t)src[i] * s.n_pad;
-          q.perm[0] = p > 0 ? o->perms + (int64_t)(p - 1) * s.N : nullptr;
-          q.padded[0] = true;
-          q.col[1] = y;
-          q.padded[1] = true;
-          int a = 2;
-          for (int other : kept)
-            if (other != src[i]) {
-              q.col[a] = cand + (int64_t)other * s.n_pad;
-              q.padded[a++] = true;
-            }
-          q.dz = a - 2;
-          q.out_index = (int)i * (s.P + 1) + p;
-          probs.push_back(q);
-        }
+  // Table [src][P+1] of I(c ; Y | kept \ {c}) for every source c in src, originals in column 0
+  // and one surrogate per round (c's rows permuted), copied to the host.
+  std::vector<double> h_tab;
+  auto source_table = [&](const std::vector<int>& src) -> int {
+    std::vector<Problem> probs;
+    probs.reserve(src.size() * (s.P + 1));
+    for (size_t i = 0; i < src.size(); ++i) {
+      for (int p = 0; p <= s.P; ++p) {
+        Problem q;
+        std::memset(&q, 0, sizeof q);
+        q.n = s.N;
+        q.dx = 1;
+        q.dy = 1;
+        q.k = o->k;
+        q.col[0] = cand + (int64_t)src[i] * s.n_pad;
+        q.perm[0] = p > 0 ? o->perms + (int64_t)(p - 1) * s.N : nullptr;
+        q.padded[0] = true;
+        q.col[1] = y;
+        q.padded[1] = true;
+        int a = 2;
+        for (int other : kept)
+          if (other != src[i]) {
+            q.col[a] = cand + (int64_t)other * s.n_pad;
+            q.padded[a++] = true;
+          }
+        q.dz = a - 2;
+        q.out_index = (int)i * (s.P + 1) + p;
+        probs.push_back(q);
       }
-      st = c->run_batch(probs, d_cmi);
+    }
+    int rc = c->run_batch(probs, d_cmi);
+    if (rc) return rc;
+    out->n_cmi += (int64_t)probs.size();
+    h_tab.resize(probs.size());
+    KSG_HIP(c, hipMemcpyAsync(h_tab.data(), d_cmi, sizeof(double) * h_tab.size(), hipMemcpyDeviceToHost,
+                              c->stream));
+    KSG_HIP(c, hipStreamSynchronize(c->stream));
+    return KSG_OK;
+  };
+  auto sources_of = [&]() {
+    std::vector<int> src;
+    for (int cidx : kept)
+      if (cidx / s.L != target) src.push_back(cidx);
+    return src;
+  };
+  if (o->prune) {
+    for (;;) {
+      const std::vector<int> src = sources_of();
+      if (src.empty()) break;
+      st = source_table(src);
       if (st) return st;
-      out->n_cmi += (int64_t)probs.size();
-      h_tab.resize(probs.size());
-      KSG_HIP(c, hipMemcpyAsync(h_tab.data(), d_cmi, sizeof(double) * h_tab.size(), hipMemcpyDeviceToHost,
-                                c->stream));
-      KSG_HIP(c, hipStreamSynchronize(c->stream));
       // minimum statistic: T_min over the originals (lowest index on ties), per-round minima
       int c_min = 0;
       for (size_t i = 1; i < src.size(); ++i)
@@ -298,17 +312,6 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   out->n_pruned = (int32_t)pruned.size();
   for (size_t i = 0; i < pruned.size() && (int)i < out->capacity; ++i)
     if (out->pruned) out->pruned[i] = pruned[i];
-  // parents: the kept candidates in inclusion order, with their inclusion step's statistics
-  for (size_t i = 0; i < incl.size(); ++i) {
-    if (std::find(kept.begin(), kept.end(), incl[i]) == kept.end()) continue;
-    if (out->n < out->capacity) {
-      if (out->var) out->var[out->n] = incl[i] / s.L;
-      if (out->lag) out->lag[out->n] = incl[i] % s.L + 1;
-      if (out->cmi) out->cmi[out->n] = incl_t[i];
-      if (out->pval) out->pval[out->n] = incl_p[i];
-    }
-    out->n++;
-  }
 
   if (o->omnibus) {
     std::vector<int> src, tgt;
@@ -350,6 +353,52 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
       out->omnibus_pval = c->h_ms[0].pval;
     }
   }
+  // ---- sequential max-statistic test of the kept sources (after a significant omnibus test) ----
+  std::vector<int> seq_removed;
+  std::vector<std::pair<int, double>> seq_p;  // (source, p-value) of every tested source
+  if (o->sequential && (!o->omnibus || !out->omnibus_tested || out->omnibus_significant)) {
+    const std::vector<int> src = sources_of();
+    if (!src.empty()) {
+      st = source_table(src);
+      if (st) return st;
+      std::vector<int32_t> sig(src.size());
+      std::vector<double> pv(src.size());
+      if (ksg_maxstat_sequential(h_tab.data(), (int32_t)src.size(), s.P, o->alpha, sig.data(), pv.data()))
+        return c->fail(KSG_EINVAL, "select_parents: sequential test");
+      // removed sources in rank order (descending original CMI, lower row first on ties)
+      std::vector<int> rank(src.size());
+      for (size_t i = 0; i < src.size(); ++i) rank[i] = (int)i;
+      std::stable_sort(rank.begin(), rank.end(),
+                       [&](int a, int b) { return h_tab[(size_t)a * (s.P + 1)] > h_tab[(size_t)b * (s.P + 1)]; });
+      for (int i : rank)
+        if (!sig[i]) seq_removed.push_back(src[i]);
+      for (size_t i = 0; i < src.size(); ++i) seq_p.emplace_back(src[i], pv[i]);
+      for (int r : seq_removed) kept.erase(std::find(kept.begin(), kept.end(), r));
+      s.selected = kept;
+    }
+  }
+  out->n_seq_removed = (int32_t)seq_removed.size();
+  for (size_t i = 0; i < seq_removed.size() && (int)i < out->capacity; ++i)
+    if (out->seq_removed) out->seq_removed[i] = seq_removed[i];
+
+  // parents: the kept candidates in inclusion order, with their inclusion step's statistics
+  for (size_t i = 0; i < incl.size(); ++i) {
+    if (std::find(kept.begin(), kept.end(), incl[i]) == kept.end()) continue;
+    if (out->n < out->capacity) {
+      if (out->var) out->var[out->n] = incl[i] / s.L;
+      if (out->lag) out->lag[out->n] = incl[i] % s.L + 1;
+      if (out->cmi) out->cmi[out->n] = incl_t[i];
+      if (out->pval) out->pval[out->n] = incl_p[i];
+      if (out->seq_pval) {
+        double v = -1.0;
+        for (const auto& e : seq_p)
+          if (e.first == incl[i]) v = e.second;
+        out->seq_pval[out->n] = v;
+      }
+    }
+    out->n++;
+  }
+
   KSG_HIP(c, hipStreamSynchronize(c->stream));
   if (out->n > out->capacity)
     return c->fail(KSG_EBUFSMALL, "select_parents: %d parents, capacity %d", out->n, out->capacity);
@@ -416,5 +465,36 @@ extern "C" int ksg_fdr_bh(const double* pvals, int32_t n, double alpha, int32_t*
     if (pvals[order[i]] <= (double)(i + 1) * alpha / n) r = i + 1;
   for (int i = 0; i < n; ++i) reject[i] = 0;
   for (int i = 0; i < r; ++i) reject[order[i]] = 1;
+  return KSG_OK;
+}
+
+extern "C" int ksg_maxstat_sequential(const double* table, int32_t rows, int32_t n_perm, double alpha,
+                                      int32_t* significant, double* pval) {
+  if (!table || !significant || !pval || rows < 0 || n_perm < 1 || !(alpha > 0 && alpha < 1)) return KSG_EINVAL;
+  const int64_t W = (int64_t)n_perm + 1;
+  std::vector<int> rank(rows);
+  for (int i = 0; i < rows; ++i) rank[i] = i;
+  // descending originals, the lower row first on ties
+  std::stable_sort(rank.begin(), rank.end(), [&](int a, int b) { return table[a * W] > table[b * W]; });
+  // every round's surrogate values in descending order: sorted[r][p] = r-th largest of round p
+  std::vector<double> sorted((size_t)rows * n_perm), col(rows);
+  for (int p = 0; p < n_perm; ++p) {
+    for (int i = 0; i < rows; ++i) col[i] = table[i * W + 1 + p];
+    std::sort(col.begin(), col.end(), std::greater<double>());
+    for (int r = 0; r < rows; ++r) sorted[(size_t)r * n_perm + p] = col[r];
+  }
+  for (int i = 0; i < rows; ++i) {
+    significant[i] = 0;
+    pval[i] = 1.0;
+  }
+  for (int r = 0; r < rows; ++r) {
+    const int i = rank[r];
+    const double t = table[i * W];
+    int count = 0;
+    for (int p = 0; p < n_perm; ++p) count += sorted[(size_t)r * n_perm + p] >= t;
+    pval[i] = (double)count / n_perm;
+    if (!(pval[i] < alpha)) break;
+    significant[i] = 1;
+  }
   return KSG_OK;
 }

@@ -101,3 +101,22 @@ def test_fdr_bh_matches_oracle():
         assert np.array_equal(ksg.fdr_bh(p, alpha), fdr_bh(p, alpha))
     with pytest.raises(ksg.KsgError):
         ksg.fdr_bh([0.1], 1.5)
+
+
+def test_maxstat_sequential_matches_oracle():
+    """The library's sequential max-statistic test (host code) against the oracle's."""
+    import paper_1807_10459_amd as ksg
+    import workloads
+    from oracle.stats import max_statistic_sequential
+    g = workloads.rng(16)
+    for _ in range(300):
+        c = int(g.integers(0, 8))
+        P = int(g.integers(1, 40))
+        t = np.round(g.standard_normal((c, P + 1)), 1)  # coarse values: ties
+        t[:, 0] += g.random() * 2.0 * (g.random(c) < 0.5)  # some clearly significant rows
+        alpha = float(g.choice([0.05, 0.2, 0.5]))
+        sig, p = ksg.maxstat_sequential(t.reshape(c, P + 1), alpha)
+        rs, rp = max_statistic_sequential(t.reshape(c, P + 1), alpha)
+        assert np.array_equal(sig, rs) and np.array_equal(p, rp)
+    with pytest.raises(ksg.KsgError):
+        ksg.maxstat_sequential(np.zeros((2, 3)), 0.0)

@@ -180,3 +180,30 @@ def test_select_parents_pruning_removal_matches_oracle(lib, ctx):
     r = ctx.select_parents(dev(data), target=target, perms=dev(perms), k=4, max_lag=L, alpha=alpha, prune=True)
     assert r["pruned"] == removed
     assert r["candidates"] == [c for c in sel if c in kept]
+
+
+def test_select_parents_sequential_matches_oracle(lib, ctx):
+    """Sequential max-statistic test of the selected sources against the oracle's, on a case in
+    which it removes one source and keeps two (logistic-map network, six of its variables, one
+    trial; found by searching seeds with the oracle)."""
+    from oracle.stats import greedy_select, sequential_final_test
+    data = np.ascontiguousarray(workloads.logistic_network(seed=136, n_trials=1, T=260).data[:, :6])
+    L, P, alpha, target = 2, 19, 0.3, 1
+    cand, y = embed(data, target=target, max_lag=L)
+    perms = workloads.permutations(y.size, P, seed=137)
+    sel, _ = greedy_select(cand, y, 4, perms, alpha=alpha)
+    kept, removed, pv, _ = sequential_final_test(cand, y, sel, target, L, 4, perms, alpha=alpha)
+    assert removed and [c for c in kept if c // L != target]  # the case removes and keeps sources
+    r = ctx.select_parents(dev(data), target=target, perms=dev(perms), k=4, max_lag=L, alpha=alpha,
+                           sequential=True)
+    assert r["seq_removed"] == removed
+    assert r["candidates"] == kept
+    for c, p in zip(r["candidates"], r["seq_pval"]):
+        assert p == (pv[c] if c // L != target else -1.0), c
+    # with the omnibus test on, the sequential test runs only after a significant omnibus result
+    r2 = ctx.select_parents(dev(data), target=target, perms=dev(perms), k=4, max_lag=L, alpha=alpha,
+                            sequential=True, omnibus=True)
+    if r2["omnibus_significant"]:
+        assert r2["seq_removed"] == removed
+    else:
+        assert r2["seq_removed"] == [] and r2["candidates"] == sel
