@@ -96,7 +96,18 @@ typedef enum ksg_option {
                                have 1-D X: -1 (default) = autotuned per conditioning dimension,
                                0 = off, 8 or 16 = forced */
   KSG_OPT_USE_GRAPH = 3,    /* 1 (default): replay greedy steps from a captured hipGraph */
-  KSG_OPT_TIMING = 4        /* 1: time every search-kernel launch with HIP events (default 0) */
+  KSG_OPT_TIMING = 4,       /* 1: time every search-kernel launch with HIP events (default 0) */
+  KSG_OPT_ALGORITHM = 5     /* KSG algorithm of every later estimate (default 1):
+                             * 1: eps_i = joint k-th neighbour distance, strict counts in XZ, YZ, Z,
+                             *    I = H_{k-1} - <H_{n_xz} + H_{n_yz} - H_{n_z}>;
+                             * 2: the k nearest neighbours (ties by the lower index) span a
+                             *    rectangle with one side per space (the largest X, Y and Z distance
+                             *    to them), counts with <= inside it,
+                             *    I = psi(k) - 2/k + <psi(n_z) - psi(n_xz) - psi(n_yz) + 1/n_xz + 1/n_yz>,
+                             *    without Z I = psi(k) - 1/k + psi(N) - <psi(n_x) + psi(n_y)>.
+                             *    counts_out then holds these counts (n_z = N-1 without Z), eps_out
+                             *    the k-th neighbour's joint distance, local_out the pointwise values.
+                             *    Problems are searched one by one (no grouping). */
 } ksg_option;
 int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
 

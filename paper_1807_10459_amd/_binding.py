@@ -213,6 +213,7 @@ class Context:
     OPT_GROUP_SIZE = 2
     OPT_USE_GRAPH = 3
     OPT_TIMING = 4
+    OPT_ALGORITHM = 5
 
     def __init__(self, device: int = 0, stream=None):
         import torch

@@ -26,7 +26,8 @@ struct alignas(16) ProbDesc {
   int32_t variant;    // shape id (see shape_id)
   int32_t out_index;  // slot in the output array
   int32_t swap_xy;    // 1: X and Y were exchanged to reach a fast shape (count rows swap back)
-  int32_t pad_[3];
+  int32_t alg;        // KSG algorithm: 1 (joint radius, strict counts) or 2 (rectangles)
+  int32_t pad_[2];
 };
 
 // G problems that share Y (1-D), Z (m columns), N and k and differ in a 1-D X column.
@@ -123,6 +124,9 @@ struct MaxStatOut {
 hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                              const double* d_htab, double* d_partials, int shape, int kp,
                              hipStream_t stream);
+// KSG algorithm 2 over the work items of problems that all have D columns.
+hipError_t launch_ksg_alg2(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
+                           const double* d_htab, double* d_partials, int D, int kp, hipStream_t stream);
 hipError_t launch_ksg_group_radius(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
                                    int n_items, float* E, int m, int G, int kp,
                                    unsigned long long* d_work, hipStream_t stream);

@@ -222,6 +222,10 @@ extern "C" int ksg_ctx_set_option(ksg_ctx* c, int option, int64_t value) {
       c->group_size = (int)value;
       return KSG_OK;
     case KSG_OPT_USE_GRAPH: c->use_graph = value != 0; return KSG_OK;
+    case KSG_OPT_ALGORITHM:
+      if (value != 1 && value != 2) return c->fail(KSG_EINVAL, "KSG algorithm must be 1 or 2");
+      c->algorithm = (int)value;
+      return KSG_OK;
     case KSG_OPT_TIMING:
       c->timing = value != 0;
       if (c->timing && !c->d_work) {
@@ -325,7 +329,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   std::vector<int> group_of(np, -1);
   std::vector<std::vector<int>> groups;  // member problem indices
   std::vector<int> group_size_of;        // G of each group's kernel
-  if (group_size != 0) {
+  if (group_size != 0 && algorithm == 1) {
     std::map<std::vector<intptr_t>, std::vector<int>> by_key;
     for (int i = 0; i < np; ++i) {
       const Problem& p = probs[i];
@@ -476,6 +480,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     d.variant = shape_id(dx, dy, p.dz);
     d.out_index = p.out_index;
     d.swap_xy = swap ? 1 : 0;
+    d.alg = algorithm;
     if (group_of[i] >= 0) {
       const int gi = group_of[i];
       const int g = (int)(std::find(groups[gi].begin(), groups[gi].end(), i) - groups[gi].begin());
@@ -491,11 +496,33 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     }
   }
 
-  // ungrouped work items
-  std::vector<Unit> units;
-  for (int r = 0; r < np; ++r)
-    if (group_of[order[r]] < 0) units.push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
-  std::vector<WorkItem> items = order_items(units);
+  // ungrouped work items (algorithm 2: one launch per column count, items in D order)
+  struct Segment {
+    int D, kp, off, count;
+  };
+  std::vector<Segment> segments;
+  std::vector<WorkItem> items;
+  if (algorithm == 2) {
+    std::map<int, std::vector<Unit>> by_d;
+    std::map<int, int> kp_of;
+    for (int r = 0; r < np; ++r) {
+      const Problem& p = probs[order[r]];
+      const int D = p.dx + p.dy + p.dz;
+      by_d[D].push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
+      const int need = p.k + 1 <= 5 ? 5 : (p.k + 1 <= 9 ? 9 : 17);
+      kp_of[D] = std::max(kp_of[D], need);
+    }
+    for (auto& kv : by_d) {
+      std::vector<WorkItem> seg = order_items(kv.second);
+      segments.push_back(Segment{kv.first, kp_of[kv.first], (int)items.size(), (int)seg.size()});
+      items.insert(items.end(), seg.begin(), seg.end());
+    }
+  } else {
+    std::vector<Unit> units;
+    for (int r = 0; r < np; ++r)
+      if (group_of[order[r]] < 0) units.push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
+    items = order_items(units);
+  }
 
   // ---- groups: descriptors, launch chunks, Y/Z count descriptors, work items ----
   // Groups of one (m, G, KP) class run as chunks of consecutive groups, each chunk three
@@ -715,7 +742,14 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
                                           stream));
     if ((st = span_end(2))) return st;
   }
-  if (!items.empty()) {
+  if (algorithm == 2) {
+    for (const Segment& g : segments) {
+      if ((st = span_begin())) return st;
+      KSG_HIP(this, launch_ksg_alg2((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
+                                    (double*)partials.ptr, g.D, g.kp, stream));
+      if ((st = span_end(3))) return st;
+    }
+  } else if (!items.empty()) {
     const int shape = common_shape;
     if ((st = span_begin())) return st;
     KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items, (int)items.size(),

@@ -237,8 +237,9 @@ hipError_t launch_embed(const float* data, int n_vars, int64_t T, int n_trials, 
 
 // ------------------------------------------------------------------ finalisation
 
-// I = H_{k-1} - S / N, S = compensated (Neumaier) sum of the problem's tile partials in tile
-// order.
+// I = C - S / N, S = compensated (Neumaier) sum of the problem's tile partials in tile order;
+// C = H_{k-1} for algorithm 1, H_{k-1} - 2/k for algorithm 2 with Z and H_{k-1} - 1/k + H_{N-1}
+// for algorithm 2 without Z.
 __global__ __launch_bounds__(256) void finalize_kernel(const ProbDesc* __restrict__ descs, int n_probs,
                                                        const double* __restrict__ partials,
                                                        const double* __restrict__ htab,
@@ -254,7 +255,9 @@ __global__ __launch_bounds__(256) void finalize_kernel(const ProbDesc* __restric
     s = u;
   }
   s += comp;
-  out[d.out_index] = htab[d.k - 1] - s / (double)d.n;
+  double c = htab[d.k - 1];
+  if (d.alg == 2) c = d.dz > 0 ? c - 2.0 / (double)d.k : (c - 1.0 / (double)d.k) + htab[d.n - 1];
+  out[d.out_index] = c - s / (double)d.n;
 }
 
 static const void* pick_search_kernel(int shape, int kp) {

@@ -1,0 +1,137 @@
+"""Parity of the HIP KSG algorithm-2 path with the CPU oracle (needs an MI355X).
+
+Neighbour rectangles, counts and the joint k-th distance must match bit for bit; CMI values
+within 1e-12 * max(|I|, 1 nat)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle.ksg import ksg_cmi
+from oracle.ksg2 import ksg2_cmi, ksg2_cmi_from_counts, ksg2_counts, ksg2_local_terms
+from tests.gpu_util import dev, soa, tol
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    c = lib.Context(0)
+    c.set_option(c.OPT_ALGORITHM, 2)
+    yield c
+    c.close()
+
+
+def _run(lib, ctx, x, y, z, k, perm=None):
+    import torch
+    n = np.asarray(x).shape[0]
+    eps = torch.empty(n, dtype=torch.float32, device="cuda")
+    cnt = torch.empty((3, n), dtype=torch.int32, device="cuda")
+    loc = torch.empty(n, dtype=torch.float64, device="cuda")
+    p = lib.Problem(soa(x), soa(y), soa(z), k, perm_x=None if perm is None else dev(perm),
+                    eps_out=eps, counts_out=cnt, local_out=loc)
+    out = ctx.cmi_batch([p])
+    torch.cuda.synchronize()
+    return eps.cpu().numpy(), cnt.cpu().numpy(), loc.cpu().numpy(), float(out.cpu()[0])
+
+
+def _check_full(lib, ctx, x, y, z, k, label=""):
+    eps, cnt, loc, cmi = _run(lib, ctx, x, y, z, k)
+    e, _, a, b, c = ksg2_counts(x, y, z, k)
+    assert np.array_equal(eps, e), label
+    assert np.array_equal(cnt[0], a) and np.array_equal(cnt[1], b) and np.array_equal(cnt[2], c), label
+    n = np.asarray(x).shape[0]
+    has_z = z is not None and np.asarray(z).size > 0
+    ref = ksg2_cmi_from_counts(n, k, a, b, c, has_z)
+    assert abs(cmi - ref) <= tol(ref), (label, cmi, ref)
+    assert np.allclose(loc, ksg2_local_terms(n, k, a, b, c, has_z), rtol=0, atol=1e-13), label
+    return cmi
+
+
+def test_worked_example(lib, ctx):
+    g = json.load(open(os.path.join(GOLD, "ksg2_tiny_ties.json")))
+    x, y, z = (np.array(g[c], np.float32) for c in "xyz")
+    assert abs(_check_full(lib, ctx, x, y, z, g["k"]) - 13 / 36) < 1e-15
+    assert abs(_check_full(lib, ctx, x, y, None, g["k"]) - 19 / 45) < 1e-15
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 0), (1, 1, 1), (1, 1, 5), (1, 2, 3), (2, 1, 2), (2, 2, 4),
+                                  (1, 1, 12), (3, 1, 2), (1, 4, 0), (2, 3, 5), (5, 5, 6), (1, 1, 14)])
+@pytest.mark.parametrize("k", [1, 4, 7, 12])
+def test_shapes_ragged(lib, ctx, dims, k):
+    n = 700 + 13 * sum(dims)
+    p = workloads.random_problem(sum(dims) * 11 + k, n, *dims, k)
+    _check_full(lib, ctx, p.x, p.y, p.z, k, str(dims))
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 8])
+def test_ties_and_duplicates(lib, ctx, k):
+    """Integer grids: many equal distances, so the index tie-break decides the neighbours."""
+    for dims in [(1, 1, 1), (2, 1, 0), (1, 2, 2)]:
+        p = workloads.random_problem(40 + k, 900, *dims, k, kind="grid")
+        _check_full(lib, ctx, p.x, p.y, p.z, k, str(dims))
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 64, 65, 255, 256, 257])
+def test_smallest_sizes(lib, ctx, n):
+    k = 1 if n < 5 else 4
+    p = workloads.random_problem(60 + n, n, 1, 1, 1, k)
+    _check_full(lib, ctx, p.x, p.y, p.z, k, str(n))
+
+
+def test_mixed_width_batch_with_surrogates(lib, ctx):
+    """One batch: problems of several column counts (one launch each) and X permutations."""
+    import torch
+    specs = [(1, 1, 2, 4), (1, 1, 0, 3), (2, 2, 3, 8), (1, 1, 2, 4), (1, 3, 6, 5)]
+    data, probs = [], []
+    perms = workloads.permutations(1500, 3, seed=71)
+    for i, (dx, dy, dz, k) in enumerate(specs):
+        pr = workloads.random_problem(70 + i, 1500, dx, dy, dz, k)
+        data.append(pr)
+        probs.append(lib.Problem(soa(pr.x), soa(pr.y), soa(pr.z), k))
+        probs.append(lib.Problem(soa(pr.x), soa(pr.y), soa(pr.z), k, perm_x=dev(perms[i % 3])))
+    out = ctx.cmi_batch(probs).cpu().numpy()
+    for i, pr in enumerate(data):
+        ref = ksg2_cmi(pr.x, pr.y, pr.z, pr.k)
+        assert abs(out[2 * i] - ref) <= tol(ref), i
+        ref_s = ksg2_cmi(pr.x[perms[i % 3]], pr.y, pr.z, pr.k)
+        assert abs(out[2 * i + 1] - ref_s) <= tol(ref_s), i
+
+
+def test_full_size_n10000(lib, ctx):
+    """N = 10,000, D = 3 (one conditioning column) in full against the oracle."""
+    p = workloads.random_problem(81, 10000, 1, 1, 1, 4)
+    _check_full(lib, ctx, p.x, p.y, p.z, 4, "n10000")
+
+
+def test_greedy_step_table_and_switch_back(lib, ctx):
+    """A greedy step under algorithm 2 against the oracle; switching back gives algorithm 1."""
+    from oracle.stats import embed
+    net = workloads.ar2_network(seed=5, T=1505, burn=200)
+    cand, y = embed(net.data, target=0, max_lag=5)
+    perms = workloads.permutations(y.size, 9, seed=82)
+    dcand, dy = ctx.embed(dev(net.data), target=0, max_lag=5)
+    pool, cond = [1, 7, 12, 20], [0, 5]
+    table, r = ctx.greedy_step(dcand, dy, pool, cond, dev(perms), k=4)
+    table = table.cpu().numpy()
+    z = np.stack([cand[c] for c in cond], axis=1)
+    for ci, c in enumerate(pool):
+        for p in (0, 3, 9):
+            xs = cand[c] if p == 0 else cand[c][perms[p - 1]]
+            ref = ksg2_cmi(xs, y, z, 4)
+            assert abs(table[ci, p] - ref) <= tol(ref), (c, p)
+    ctx.set_option(ctx.OPT_ALGORITHM, 1)
+    try:
+        t1, _ = ctx.greedy_step(dcand, dy, pool, cond, dev(perms), k=4)
+        ref1 = ksg_cmi(cand[pool[0]], y, z, 4)
+        assert abs(float(t1[0, 0]) - ref1) <= tol(ref1)
+    finally:
+        ctx.set_option(ctx.OPT_ALGORITHM, 2)
+
+
+def test_bad_algorithm_rejected(lib, ctx):
+    with pytest.raises(lib.KsgError):
+        ctx.set_option(ctx.OPT_ALGORITHM, 3)
