@@ -50,14 +50,15 @@ def forced_order(net, n_vars=5, L=MAX_LAG, seed=1):
 
 
 def _cpu_task(args):
-    cand_c, y, z, k = args
+    cand_c, y, z, k, alg = args
     from oracle.ksg import ksg_cmi
+    from oracle.ksg2 import ksg2_cmi
     t0 = time.perf_counter()
-    v = ksg_cmi(cand_c, y, z, k)
+    v = (ksg2_cmi if alg == 2 else ksg_cmi)(cand_c, y, z, k)
     return v, time.perf_counter() - t0
 
 
-def cpu_baseline(cand, y, perms, order, sample_per_m=2, workers=None):
+def cpu_baseline(cand, y, perms, order, sample_per_m=2, workers=None, alg=1):
     """The oracle on a bounded sample of the step's CMIs: (CMI/s, cores, description, values)."""
     import multiprocessing as mp
     tasks, keys = [], []
@@ -68,7 +69,7 @@ def cpu_baseline(cand, y, perms, order, sample_per_m=2, workers=None):
             ci = (3 * s + m) % len(pool)
             p = s  # round s (0 = original)
             x = cand[pool[ci]] if p == 0 else cand[pool[ci]][perms[p - 1]]
-            tasks.append((x, y, z, K))
+            tasks.append((x, y, z, K, alg))
             keys.append((m, ci, p))
     workers = workers or min(8, os.cpu_count() or 1)
     t0 = time.perf_counter()
@@ -310,7 +311,9 @@ KERNEL_NAMES = {"radius": "ksg_group_radius_kernel (k-NN radius of each problem 
                 "yz_count": "ksg_yzcount_kernel (n_YZ and n_Z of every problem of a step at once: "
                             "rank histogram over the sorted radii)",
                 "x_count": "ksg_group_xcount_kernel (n_XZ of each problem of a group, digamma partial sums)",
-                "single": "ksg_batch_kernel (brute-force radius, counts and digamma partial sums)"}
+                "single": "ksg_batch_kernel (brute-force radius, counts and digamma partial sums)",
+                "alg2": "ksg_alg2_kernel (KSG algorithm 2: indexed top-k, neighbour rectangles, "
+                        "rectangle counts and partial sums)"}
 
 
 def _kernel_source_hash():
@@ -338,6 +341,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--algorithm", type=int, default=1, choices=[1, 2],
+                    help="KSG algorithm of the estimates (2: neighbour rectangles, searched one by one)")
     ap.add_argument("--group-size", type=int, default=-1,
                     help="problems searched together (-1 tuned, 0 off, 8, 16)")
     ap.add_argument("--workload", default="ar2", choices=["ar2", "c4", "modes", "omnibus"],
@@ -425,9 +430,10 @@ def main():
     perms = torch.from_numpy(perms_np).cuda()
     ctx = ksg.Context(0)
     t_tune = time.perf_counter()
-    tuned = ctx.autotune(8192) if args.group_size == -1 else None
+    tuned = ctx.autotune(8192) if (args.group_size == -1 and args.algorithm == 1) else None
     t_tune = time.perf_counter() - t_tune
     ctx.set_option(ctx.OPT_GROUP_SIZE, args.group_size)
+    ctx.set_option(ctx.OPT_ALGORITHM, args.algorithm)
     tables = {m: torch.empty((25 - m, N_PERM + 1), dtype=torch.float64, device="cuda") for m in FORCED_M}
 
     def step():
@@ -474,7 +480,7 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_VALU, 4),
         "traffic": _traffic_record(dom),
-        "kernel": KERNEL_NAMES[dom],
+        "kernel": KERNEL_NAMES["alg2"] if args.algorithm == 2 else KERNEL_NAMES[dom],
         "kernel_ms_per_launch": round(d_ms / d_n, 3),
         "launches": d_n,
         "ops_per_launch": d_ops / d_n,
@@ -497,7 +503,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "AR(2) 5-node greedy selection, target 0, N=10000, 25 candidates, "
                                "k=4, 200 surrogates, conditioning dims m=1..8 (forced path), "
-                               f"{n_cmi} CMIs per step",
+                               f"{n_cmi} CMIs per step" + (", KSG algorithm 2" if args.algorithm == 2 else ""),
                    "n_cmi_per_step": n_cmi},
         "roofline": roofline,
         "search": search,
@@ -517,7 +523,7 @@ def main():
     if not args.no_cpu_baseline:
         cand_np = cand.cpu().numpy()
         y_np = y.cpu().numpy()
-        cps, cores, desc, vals = cpu_baseline(cand_np, y_np, perms_np, order)
+        cps, cores, desc, vals = cpu_baseline(cand_np, y_np, perms_np, order, alg=args.algorithm)
         # The sampled oracle values double as a parity spot check of the timed run.
         worst = 0.0
         for (m, ci, p), v in vals.items():

@@ -29,10 +29,8 @@ __device__ __forceinline__ void topk_insert_index(float (&b)[KP], int (&bi)[KP],
   for (int s = KP - 1; s >= 1; --s) {
     const bool shift = v < b[s - 1];
     const bool place = v < b[s];
-    const float nb = shift ? b[s - 1] : (place ? v : b[s]);
-    const int ni = shift ? bi[s - 1] : (place ? j : bi[s]);
-    b[s] = nb;
-    bi[s] = ni;
+    bi[s] = shift ? bi[s - 1] : (place ? j : bi[s]);
+    b[s] = __builtin_amdgcn_fmed3f(b[s - 1], b[s], v);  // = shift ? b[s-1] : min(b[s], v)
   }
   if (v < b[0]) {
     b[0] = v;
@@ -163,8 +161,11 @@ __global__ __launch_bounds__(kTileQ) void ksg_alg2_kernel(const ProbDesc* __rest
 #pragma unroll
     for (int u = 0; u < U; ++u) hit |= d[u] < b[KP - 1];
     if (hit) {
+      // one branch per candidate: a wave runs an insertion only when one of its lanes has that
+      // candidate below its current k+1-th distance
 #pragma unroll
-      for (int u = 0; u < U; ++u) topk_insert_index<KP>(b, bi, d[u], j + u);
+      for (int u = 0; u < U; ++u)
+        if (d[u] < b[KP - 1]) topk_insert_index<KP>(b, bi, d[u], j + u);
     }
   }
 
