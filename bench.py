@@ -392,19 +392,25 @@ def main():
         ctx.select_parents(data, 0, perms, k=K, max_lag=MAX_LAG, max_steps=1)  # warm-up
         true_src = sorted({s_ for (s_, t_, _) in net.edges if t_ == 0})
         out = {}
-        for mode, prune in (("mte", False), ("mte", True), ("bte", False), ("mmi", False)):
+        runs = (("mte", False, False, 1), ("mte", True, False, 1), ("mte", True, True, 1),
+                ("bte", False, False, 1), ("mmi", False, False, 1), ("mte", False, False, 2))
+        for mode, prune, seq, alg in runs:
+            ctx.set_option(ctx.OPT_ALGORITHM, alg)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = ctx.select_parents(data, 0, perms, k=K, max_lag=MAX_LAG, mode=mode, prune=prune, omnibus=True)
+            r = ctx.select_parents(data, 0, perms, k=K, max_lag=MAX_LAG, mode=mode, prune=prune, omnibus=True,
+                                   sequential=seq)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             srcs = sorted({v for (v, _) in r["parents"] if v != 0})
-            out[mode + ("+prune" if prune else "")] = {
+            name = mode + ("+prune" if prune else "") + ("+seq" if seq else "") + (" (KSG 2)" if alg == 2 else "")
+            out[name] = {
                 "seconds": round(dt, 3), "cmi_per_s": round(r["n_cmi"] / dt, 1), "n_cmi": r["n_cmi"],
                 "steps": r["n_steps"], "parents": r["parents"], "pruned": r["pruned"],
+                "seq_removed": r["seq_removed"], "seq_pval": [round(v, 4) for v in r["seq_pval"]],
                 "source_vars": srcs, "omnibus_pval": r["omnibus_pval"]}
-            print(f"{mode} prune={prune}: {dt:.2f} s, {r['n_cmi']} CMIs, parents {r['parents']}",
-                  file=sys.stderr, flush=True)
+            print(f"{name}: {dt:.2f} s, {r['n_cmi']} CMIs, parents {r['parents']}", file=sys.stderr, flush=True)
+        ctx.set_option(ctx.OPT_ALGORITHM, 1)
         print(json.dumps({"workload": "selection variants, AR(2) 5-node network, target 0, N=10000, "
                                       "k=4, 200 surrogates", "true_source_vars": true_src, "runs": out}))
         return
