@@ -133,6 +133,53 @@ def c4_dataset(ctx, plan, log=print):
     return feats, targ, obs, net_id
 
 
+def _margins(pred, obs, rate):
+    """Gate margins by the rule of ksg_gate_calibrate: u = (obs - p05) / |p01 - p05|; each margin
+    the smallest value >= 0 leaving at most floor(rate/2 * B) examples decided wrongly on its side."""
+    s = np.maximum(np.abs(pred[:, 1] - pred[:, 0]), 1e-30)
+    u = (obs[:, 0] - pred[:, 0]) / s
+    sig = obs[:, 1] > 0.5
+    allow = int(np.floor(rate / 2 * len(u)))
+    un = np.sort(u[~sig])[::-1]
+    up = np.sort(u[sig])
+    hi = max(0.0, float(un[allow])) if un.size > allow else 0.0
+    lo = max(0.0, float(-up[allow])) if up.size > allow else 0.0
+    return lo, hi, u
+
+
+def bucket_table_ablation(F, Tg, HF, HO, rate, eval_steps):
+    """The gate driven by a mean-threshold table instead of the network: the training targets
+    averaged per (log N to 0.1, log c in steps of 0.5) bucket (the global mean for an empty
+    bucket), calibrated on the same held-out examples at the same rate.  Reports its held-out
+    fallback fraction and, on the evaluation run's judged steps (N, c, t_obs, plain decision),
+    the steps it would decide, leave to the surrogates, and decide wrongly."""
+    def key(logn, logc):
+        return (round(float(logn), 1), int(np.floor(float(logc) / 0.5)))
+    table = {}
+    for f, t in zip(F, Tg):
+        table.setdefault(key(f[0], f[5]), []).append(t)
+    means = {kk: np.mean(v, axis=0) for kk, v in table.items()}
+    glob = Tg.mean(axis=0)
+
+    def predict(logn, logc):
+        return means.get(key(logn, logc), glob)
+    pred = np.array([predict(f[0], f[5]) for f in HF])
+    lo, hi, u = _margins(pred, HO, rate)
+    band = (u <= hi) & (u >= -lo)
+    decided, fallback, wrong = 0, 0, 0
+    for (n, c, t_obs, plain) in eval_steps:
+        p05, p01 = predict(np.log(n), np.log(c))
+        uu = (np.sqrt(n) * t_obs - p05) / max(abs(p01 - p05), 1e-30)
+        if uu > hi or uu < -lo:
+            decided += 1
+            wrong += int((uu > hi) != (plain == 1))
+        else:
+            fallback += 1
+    return {"margin_lo": round(lo, 4), "margin_hi": round(hi, 4), "buckets": len(means),
+            "held_out_fallback": round(float(band.mean()), 4),
+            "eval_steps_decided": decided, "eval_steps_fallback": fallback, "eval_steps_wrong": wrong}
+
+
 def c4_evaluate(ctx, args, log):
     """Learned-null vs plain greedy selection on the 20-node logistic network (seed 3)."""
     import torch
@@ -197,6 +244,16 @@ def c4_evaluate(ctx, args, log):
     steps_judged = sum(r["n_steps"] for r in plain.values())
     disagree = sum(r["n_disagree"] for r in plain.values())
     true_edges = {(s_, t_) for (s_, t_, _) in net3.edges}
+    # ablation: the same gate driven by a per-(N, c) bucket mean-threshold table, evaluated on
+    # the plain run's judged steps (pool size c = 100 - step in the multivariate-TE pool)
+    eval_steps = [(N, 20 * MAX_LAG - i, st["t_obs"], st["plain"])
+                  for r in plain.values() for i, st in enumerate(r["steps"]) if st["plain"] in (0, 1)]
+    ablation = bucket_table_ablation(feats[tr].cpu().numpy(), targ[tr].cpu().numpy(),
+                                     feats[hi_idx].cpu().numpy(), obs[hi_idx].cpu().numpy(), 0.0025, eval_steps)
+    ablation["network_held_out_fallback"] = round(cal["fallback"], 4)
+    ablation["network_eval_steps_decided"] = sum(1 for r in plain.values() for st in r["steps"]
+                                                 if st["verdict"] in (-1, 1))
+    log(f"ablation: {ablation}")
     return {
         "metric": "parents/sec learned vs plain null (20-node logistic network, N=29950, 500 surrogates)",
         "value": round(n_par_learned / t_learned, 4),
@@ -218,6 +275,7 @@ def c4_evaluate(ctx, args, log):
         "training": {"examples": int(feats.shape[0]), "held_out": int(hi_idx.numel()),
                      "dataset_s": round(t_data, 1), "train_s": round(t_train, 1),
                      "loss_first": hist[0], "loss_last": hist[-1]},
+        "ablation_bucket_table": ablation,
         "true_source_edges_found_plain": sum(1 for t in targets for v in sources(plain[t], t)
                                              if v != t and (v, t) in true_edges),
         "true_source_edges": sum(1 for t in targets for (s_, t_) in true_edges if t_ == t),
