@@ -275,6 +275,14 @@ int ksg_greedy_step(ksg_ctx* ctx, const float* cand, const float* y, int64_t N, 
  * the minimising source is removed and the test repeats, else the rest are kept.  The
  * omnibus test, when asked for, runs on the pruned set.
  *
+ * Sequential max-statistic test (sequential = 1), after pruning and, when the omnibus test was
+ * asked for, only if it is significant: each kept source c gets I(c ; Y | every other kept
+ * candidate) and its surrogates as for pruning, and the table goes through
+ * ksg_maxstat_sequential; sources it does not find significant are removed from the parents
+ * (seq_removed) and the kept sources' p-values are reported (seq_pval).
+ *
+ * Every estimate uses the context's KSG algorithm (KSG_OPT_ALGORITHM).
+ *
  * Learned null: learned != NULL gates each step first with the threshold
  * network (ksg_mlp) evaluated on the step's feature vector; only steps whose
  * t_obs lies within [tau05_hat - margin_lo*s, tau05_hat + margin_hi*s],

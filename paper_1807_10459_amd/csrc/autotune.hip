@@ -90,10 +90,20 @@ extern "C" int ksg_autotune(ksg_ctx* c, int64_t n, const char* cache_path, int32
     KSG_HIP(c, hipGetLastError());
     st = c->reserve(c->cmi, sizeof(double) * n_x, "tuning output");
     if (st) return st;
-    const bool was_timing = c->timing;
-    const bool was_check = c->check_finite;
-    const int was_group = c->group_size;
+    // the context's settings come back on every exit, errors included
+    struct Restore {
+      ksg_ctx* c;
+      bool timing, check;
+      int group, alg;
+      ~Restore() {
+        c->timing = timing;
+        c->check_finite = check;
+        c->group_size = group;
+        c->algorithm = alg;
+      }
+    } restore{c, c->timing, c->check_finite, c->group_size, c->algorithm};
     c->check_finite = false;
+    c->algorithm = 1;  // the group size only matters to algorithm 1 (algorithm 2 is not grouped)
     for (int t = 0; t < 2; ++t) {
       const int k = t == 0 ? 4 : 8;
       for (int m = 0; m <= 14; ++m) {
@@ -121,11 +131,7 @@ extern "C" int ksg_autotune(ksg_ctx* c, int64_t n, const char* cache_path, int32
             if (!e0 || !e1) return c->fail(KSG_EDEVICE, "events");
             KSG_HIP(c, hipEventRecord(e0, c->stream));
             st = c->run_batch(probs, (double*)c->cmi.ptr);
-            if (st) {
-              c->group_size = was_group;
-              c->check_finite = was_check;
-              return st;
-            }
+            if (st) return st;
             KSG_HIP(c, hipEventRecord(e1, c->stream));
             KSG_HIP(c, hipEventSynchronize(e1));
             float ms = 0.0f;
@@ -142,9 +148,6 @@ extern "C" int ksg_autotune(ksg_ctx* c, int64_t n, const char* cache_path, int32
         c->tuned_g[t][m] = best_g;
       }
     }
-    c->group_size = was_group;
-    c->check_finite = was_check;
-    c->timing = was_timing;
     if (cache_path) save_cache(c, cache_path);
   }
   if (tuned_out)

@@ -135,3 +135,10 @@ def test_greedy_step_table_and_switch_back(lib, ctx):
 def test_bad_algorithm_rejected(lib, ctx):
     with pytest.raises(lib.KsgError):
         ctx.set_option(ctx.OPT_ALGORITHM, 3)
+
+
+def test_autotune_keeps_algorithm(lib, ctx):
+    """The autotuner times algorithm-1 groups and leaves the context on algorithm 2."""
+    ctx.autotune(1024)
+    p = workloads.random_problem(91, 800, 1, 1, 2, 4)
+    _check_full(lib, ctx, p.x, p.y, p.z, 4, "after autotune")
