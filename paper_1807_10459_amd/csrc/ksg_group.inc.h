@@ -120,6 +120,7 @@ __device__ __forceinline__ void group_radius_tile(const float* __restrict__ base
 
   unsigned bmax = __float_as_uint(INFINITY);
   unsigned done = 0;    // problem-steps whose per-problem work ran (wave-uniform)
+  const unsigned gmask = (1u << ng) - 1u;  // the group's real problems (ng <= 16)
   unsigned shared = 0;  // shared-part operations / 256 (wave-uniform)
 
   // One reference step s; dir != 0: a window step, skipped (returns true) when every lane's
@@ -157,21 +158,24 @@ __device__ __forceinline__ void group_radius_tile(const float* __restrict__ base
     const unsigned dmin = min(min(__float_as_uint(dyz[0]), __float_as_uint(dyz[1])),
                               min(__float_as_uint(dyz[2]), __float_as_uint(dyz[3])));
     if (__builtin_amdgcn_ballot_w64(dmin < bmax) == 0) return false;
+    unsigned act = 0;  // problems whose work ran in this step (bit g; wave-uniform, kept scalar)
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if (__builtin_amdgcn_ballot_w64(dmin < __float_as_uint(b[g][KP - 1])) == 0) continue;
-      done += g < ng ? 1u : 0u;
+      act |= 1u << g;
       float d[U];
       d[0] = __builtin_amdgcn_fmed3f(fabsf(rx[g].x - qx[g]), dyz[0], INFINITY);
       d[1] = __builtin_amdgcn_fmed3f(fabsf(rx[g].y - qx[g]), dyz[1], INFINITY);
       d[2] = __builtin_amdgcn_fmed3f(fabsf(rx[g].z - qx[g]), dyz[2], INFINITY);
       d[3] = __builtin_amdgcn_fmed3f(fabsf(rx[g].w - qx[g]), dyz[3], INFINITY);
-      const unsigned lo = min(min(__float_as_uint(d[0]), __float_as_uint(d[1])),
-                              min(__float_as_uint(d[2]), __float_as_uint(d[3])));
+      // chained so that it is one v_min_u32 and one v_min3_u32
+      const unsigned lo = min(min(min(__float_as_uint(d[0]), __float_as_uint(d[1])), __float_as_uint(d[2])),
+                              __float_as_uint(d[3]));
       if (lo < __float_as_uint(b[g][KP - 1]))
         topk_insert4<KP>(b[g], __float_as_uint(d[0]), __float_as_uint(d[1]), __float_as_uint(d[2]),
-                         __float_as_uint(d[3]));
+                         __float_as_uint(d[3]), lo);
     }
+    done += __builtin_popcount(__builtin_amdgcn_readfirstlane(act) & gmask);
     bmax = __float_as_uint(b[0][KP - 1]);
 #pragma unroll
     for (int g = 1; g < G; ++g) bmax = max(bmax, __float_as_uint(b[g][KP - 1]));
@@ -376,6 +380,7 @@ __device__ __forceinline__ void group_xcount_tile(const float* __restrict__ base
   for (int g = 1; g < G; ++g) emax = max(emax, __float_as_uint(eps[g]));
   unsigned done = 0;
   unsigned shared = 0;
+  const unsigned gmask = (1u << gd->ng) - 1u;  // the group's real problems (ng <= 16)
   int own = wr.s_lo, r = wr.s_hi + 1, l = wr.s_lo - 1;
   bool ract = wr.live && r < steps, lact = wr.live && l >= 0;
   for (;;) {
@@ -431,12 +436,13 @@ __device__ __forceinline__ void group_xcount_tile(const float* __restrict__ base
     ksg_f4 rx[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) rx[g] = px[s * G + g];
+    unsigned act = 0;  // problems whose work ran in this step (bit g; wave-uniform, kept scalar)
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       if constexpr (M > 0) {
         if (__builtin_amdgcn_ballot_w64(zmin < __float_as_uint(eps[g])) == 0) continue;
       }
-      done += g < ng ? 1u : 0u;
+      act |= 1u << g;
       const float t[U] = {fabsf(rx[g].x - qx[g]), fabsf(rx[g].y - qx[g]), fabsf(rx[g].z - qx[g]),
                           fabsf(rx[g].w - qx[g])};
 #pragma unroll
@@ -445,6 +451,7 @@ __device__ __forceinline__ void group_xcount_tile(const float* __restrict__ base
         cxz[g] += (unsigned)(dxz < eps[g]);
       }
     }
+    done += __builtin_popcount(__builtin_amdgcn_readfirstlane(act) & gmask);
   }
 
   // ---- epilogue: self correction, digamma terms, one partial per (problem, tile) ----

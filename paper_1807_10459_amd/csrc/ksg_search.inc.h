@@ -55,12 +55,13 @@ __device__ __forceinline__ void topk_insert_sorted(float (&b)[KP], float v) {
   b[0] = __int_as_float(min(__float_as_int(b[0]), __float_as_int(v)));
 }
 
+// s0 = min(a0, a1, a2, a3), which the caller has already computed for its test.
 template <int KP>
 __device__ __forceinline__ void topk_insert4(float (&b)[KP], unsigned a0, unsigned a1, unsigned a2,
-                                             unsigned a3) {
+                                             unsigned a3, unsigned s0) {
   const unsigned p = min(a0, a1), q = max(a0, a1), r = min(a2, a3), t = max(a2, a3);
   const unsigned mid_lo = max(p, r), mid_hi = min(q, t);
-  const unsigned s0 = min(p, r), s1 = min(mid_lo, mid_hi);
+  const unsigned s1 = min(mid_lo, mid_hi);
   topk_insert_sorted<KP>(b, __uint_as_float(s0));
   if (__builtin_amdgcn_ballot_w64(s1 < __float_as_uint(b[KP - 1])) != 0) {
     topk_insert_sorted<KP>(b, __uint_as_float(s1));
