@@ -246,7 +246,7 @@ def c4_evaluate(ctx, args, log):
     true_edges = {(s_, t_) for (s_, t_, _) in net3.edges}
     # ablation: the same gate driven by a per-(N, c) bucket mean-threshold table, evaluated on
     # the plain run's judged steps (pool size c = 100 - step in the multivariate-TE pool)
-    eval_steps = [(N, 20 * MAX_LAG - i, st["t_obs"], st["plain"])
+    eval_steps = [(N, n_vars * MAX_LAG - i, st["t_obs"], st["plain"])
                   for r in plain.values() for i, st in enumerate(r["steps"]) if st["plain"] in (0, 1)]
     ablation = bucket_table_ablation(feats[tr].cpu().numpy(), targ[tr].cpu().numpy(),
                                      feats[hi_idx].cpu().numpy(), obs[hi_idx].cpu().numpy(), 0.0025, eval_steps)
