@@ -132,24 +132,25 @@ def max_statistic(cmi: np.ndarray, alpha: float = 0.05) -> MaxStat:
                    order_statistic_threshold(t_max, 0.01), t_max)
 
 
-def _step_cmis(cand, y, zcols, pool, perms, k):
+def _step_cmis(cand, y, zcols, pool, perms, k, estimator=ksg_cmi):
     P = perms.shape[0]
     z = np.stack(zcols, axis=1) if zcols else np.zeros((y.size, 0), np.float32)
     out = np.empty((len(pool), P + 1), dtype=np.float64)
     for ci, c in enumerate(pool):
-        out[ci, 0] = ksg_cmi(cand[c], y, z, k)
+        out[ci, 0] = estimator(cand[c], y, z, k)
         for p in range(P):
-            out[ci, p + 1] = ksg_cmi(cand[c][perms[p]], y, z, k)
+            out[ci, p + 1] = estimator(cand[c][perms[p]], y, z, k)
     return out
 
 
 def greedy_select(cand, y, k: int, perms, alpha: float = 0.05, max_steps: int | None = None,
-                  return_cmis: bool = False, pool=None, selected=None):
+                  return_cmis: bool = False, pool=None, selected=None, estimator=ksg_cmi):
     """Greedy CMI-maximising selection gated by the max-statistic test.
 
     cand: [C][N] FP32 candidate columns, y: [N] FP32, perms: int [P][N].  pool: candidate
     indices to choose from (default: all); selected: the initial conditioning set (default:
-    empty), extended in place of a copy.
+    empty), extended in place of a copy.  estimator: the CMI function (X, Y, Z, k) -> nats
+    (KSG algorithm 1 by default; oracle.ksg2.ksg2_cmi for algorithm 2).
     Returns (selected candidate indices in inclusion order, per-step MaxStat list[, per-step
     CMI tables]); the returned selection starts with the initial set.
     """
@@ -160,7 +161,7 @@ def greedy_select(cand, y, k: int, perms, alpha: float = 0.05, max_steps: int | 
     selected = [] if selected is None else list(selected)
     steps, tables = [], []
     while pool and len(selected) < MAX_COND and (max_steps is None or len(steps) < max_steps):
-        cmis = _step_cmis(cand, y, [cand[s] for s in selected], pool, perms, k)
+        cmis = _step_cmis(cand, y, [cand[s] for s in selected], pool, perms, k, estimator)
         ms = max_statistic(cmis, alpha)
         steps.append(ms)
         tables.append(cmis)

@@ -207,3 +207,24 @@ def test_select_parents_sequential_matches_oracle(lib, ctx):
         assert r2["seq_removed"] == removed
     else:
         assert r2["seq_removed"] == [] and r2["candidates"] == sel
+
+
+def test_select_parents_algorithm2_matches_oracle(lib, ctx):
+    """select_parents under KSG algorithm 2 equals the oracle's greedy selection with the
+    algorithm-2 estimator, step by step."""
+    from oracle.ksg2 import ksg2_cmi
+    data = _small_chain(31)
+    L, P = 2, 19
+    cand, y = embed(data, target=3, max_lag=L)
+    perms = workloads.permutations(y.size, P, seed=32)
+    sel, steps = greedy_select(cand, y, 4, perms, alpha=0.05, estimator=ksg2_cmi)
+    ctx.set_option(ctx.OPT_ALGORITHM, 2)
+    try:
+        r = ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=L, alpha=0.05)
+    finally:
+        ctx.set_option(ctx.OPT_ALGORITHM, 1)
+    assert r["candidates"] == sel
+    assert r["n_steps"] == len(steps)
+    for i, s in enumerate(steps[:len(sel)]):
+        assert abs(r["cmi"][i] - s.t_obs) <= tol(s.t_obs)
+        assert r["pval"][i] == s.pval
