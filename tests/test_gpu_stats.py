@@ -228,3 +228,32 @@ def test_select_parents_algorithm2_matches_oracle(lib, ctx):
     for i, s in enumerate(steps[:len(sel)]):
         assert abs(r["cmi"][i] - s.t_obs) <= tol(s.t_obs)
         assert r["pval"][i] == s.pval
+
+
+def test_bench_configuration_sampled_parity(lib, ctx):
+    """The timed workload at full size: AR(2) network, N = 10,000, 25 candidates, 200
+    surrogates, greedy steps with m = 1 and m = 8 conditioning columns, one grouped batched
+    launch each (as the benchmark runs them).  Sampled CMIs of every step equal the oracle's;
+    the step's max-statistic result equals the oracle's test on the returned table."""
+    net = workloads.ar2_network(seed=1)
+    L, P = 5, 200
+    perms = workloads.permutations(10000, P, seed=11)
+    cand, y = embed(net.data, target=0, max_lag=L)
+    dcand, dy = ctx.embed(dev(net.data), target=0, max_lag=L)
+    first = [0, 1] + [src * L + (lag - 1) for (src, _, lag) in net.edges]
+    order = first + [c for c in range(25) if c not in first]
+    g = workloads.rng(77)
+    for m in (1, 8):
+        cond = order[:m]
+        pool = [c for c in range(25) if c not in cond]
+        table, r = ctx.greedy_step(dcand, dy, pool, cond, dev(perms), k=4)
+        table = table.cpu().numpy()
+        ms = max_statistic(table, 0.05)
+        assert r["c_star"] == ms.c_star and r["count"] == ms.count and r["significant"] == ms.significant
+        z = np.stack([cand[c] for c in cond], axis=1)
+        samples = {(ms.c_star, 0), (len(pool) - 1, P)} | {(int(g.integers(len(pool))), int(g.integers(P + 1)))
+                                                          for _ in range(3)}
+        for ci, p in sorted(samples):
+            xs = cand[pool[ci]] if p == 0 else cand[pool[ci]][perms[p - 1]]
+            ref = ksg_cmi(xs, y, z, 4)
+            assert abs(table[ci, p] - ref) <= tol(ref), (m, ci, p)
