@@ -448,7 +448,10 @@ __device__ __forceinline__ void group_xcount_tile(const float* __restrict__ base
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const float dxz = M > 0 ? fmaxf(t[u], dz[u]) : t[u];
-        cxz[g] += (unsigned)(dxz < eps[g]);
+        // dxz < eps exactly when fl(dxz - eps) is negative (denormals kept, so the difference
+        // of two distinct values is never zero): the sign bit is the count increment, with a
+        // subtract and a shift that both read only VGPRs
+        cxz[g] += __float_as_uint(dxz - eps[g]) >> 31;
       }
     }
     done += __builtin_popcount(__builtin_amdgcn_readfirstlane(act) & gmask);
