@@ -121,7 +121,7 @@ __device__ __forceinline__ unsigned ordered_bits(float v) {
 __global__ __launch_bounds__(256) void key_order_kernel(const GroupDesc* __restrict__ descs,
                                                         int n_groups, float* __restrict__ base) {
   constexpr int kChunk = 2048;
-  __shared__ unsigned s_key[kChunk];
+  __shared__ __align__(16) unsigned s_key[kChunk];
   for (int gi = blockIdx.y; gi < n_groups; gi += gridDim.y) {
     const GroupDesc& gd = descs[gi];
     const int n = gd.n;
@@ -139,12 +139,22 @@ __global__ __launch_bounds__(256) void key_order_kernel(const GroupDesc* __restr
     int rank = 0;
     for (int j0 = 0; j0 < n; j0 += kChunk) {
       const int cnt = min(kChunk, n - j0);
+      const int cnt4 = (cnt + 3) & ~3;
       __syncthreads();
-      for (int t = threadIdx.x; t < cnt; t += 256) s_key[t] = ordered_bits(key[j0 + t]);
+      // entries cnt..cnt4-1 hold the largest key; their row index j0 + t >= n exceeds every i,
+      // so they never rank below a real row
+      for (int t = threadIdx.x; t < cnt4; t += 256) s_key[t] = t < cnt ? ordered_bits(key[j0 + t]) : ~0u;
       __syncthreads();
-      for (int t = 0; t < cnt; ++t) {
-        const unsigned long long kj = ((unsigned long long)s_key[t] << 32) | (unsigned)(j0 + t);
-        rank += kj < ki ? 1 : 0;
+      // four keys per LDS read, several reads in flight
+      const uint4* s4 = reinterpret_cast<const uint4*>(s_key);
+#pragma unroll 4
+      for (int t4 = 0; t4 < cnt4 / 4; ++t4) {
+        const uint4 v = s4[t4];
+        const unsigned j = (unsigned)(j0 + 4 * t4);
+        rank += ((((unsigned long long)v.x << 32) | j) < ki) ? 1 : 0;
+        rank += ((((unsigned long long)v.y << 32) | (j + 1)) < ki) ? 1 : 0;
+        rank += ((((unsigned long long)v.z << 32) | (j + 2)) < ki) ? 1 : 0;
+        rank += ((((unsigned long long)v.w << 32) | (j + 3)) < ki) ? 1 : 0;
       }
     }
     if (i < n) sigma[rank] = i;
