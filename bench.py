@@ -337,7 +337,8 @@ def omnibus_bench(ksg, args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (FP32 differences/compares, FP64 digamma sums)",
+        "dtype": "f32",
+        "dtype_note": "FP32 differences, maxima and compares; FP64 only in the digamma sums",
         "data": "synthetic",
         "config": {"workload": f"omnibus test of target 0's parent set, 20-node logistic network, "
                                f"N={N}, {len(src)} source + 1 target + {len(tgt)} target-past columns "
@@ -563,7 +564,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (FP32 differences/compares, FP64 digamma sums)",
+        "dtype": "f32",
+        "dtype_note": "FP32 differences, maxima and compares; FP64 only in the digamma sums",
         "data": "synthetic",
         "config": {"workload": "AR(2) 5-node greedy selection, target 0, N=10000, 25 candidates, "
                                "k=4, 200 surrogates, conditioning dims m=1..8 (forced path), "
