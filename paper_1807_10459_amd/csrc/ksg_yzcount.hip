@@ -21,6 +21,7 @@
 namespace ksg {
 
 constexpr int kYZThreads = 256;
+constexpr int kYZBuckets = 256;  // radius buckets of the rank search
 
 template <int M>
 __global__ __launch_bounds__(kYZThreads) void ksg_yzcount_kernel(const float* __restrict__ base,
@@ -34,6 +35,7 @@ __global__ __launch_bounds__(kYZThreads) void ksg_yzcount_kernel(const float* __
   __shared__ unsigned s_hz[kYZSlots + 1];
   __shared__ unsigned s_hyz[kYZSlots + 1];
   __shared__ unsigned s_part[2][kYZThreads];
+  __shared__ int s_start[kYZBuckets + 2];  // first sorted slot of each radius bucket
   constexpr int W = M + 1;
   const int tid = threadIdx.x;
   const WorkItem it = items[blockIdx.x];
@@ -84,13 +86,35 @@ __global__ __launch_bounds__(kYZThreads) void ksg_yzcount_kernel(const float* __
   }
   const float rmax = __uint_as_float((unsigned)(s_key[nv - 1] >> 32));
 
-  // pos(d) = number of radii <= d (entries past nv are ~0 and never <= a distance)
+  // pos(d) = number of radii <= d.  The radii are non-negative, so their bit patterns order
+  // like their values; bucket(x) = (x - r_lo) >> shift maps [r_lo, r_hi] monotonically onto at
+  // most kYZBuckets buckets, s_start[b] = the first sorted slot whose bucket is >= b.  Every
+  // radius of a lower bucket is < d and every radius of a higher bucket is > d, so pos(d) =
+  // s_start[b] + #{radii of bucket b that are <= d}, found by a short binary search.
+  const unsigned r_lo = (unsigned)(s_key[0] >> 32), r_hi = (unsigned)(s_key[nv - 1] >> 32);
+  const unsigned span = r_hi - r_lo;  // r_hi >= r_lo
+  int shift = 0;
+  while ((span >> shift) >= (unsigned)kYZBuckets) ++shift;
+  for (int i = tid; i < nv; i += kYZThreads) {
+    const int b = (int)(((unsigned)(s_key[i] >> 32) - r_lo) >> shift);
+    const int bp = i == 0 ? -1 : (int)(((unsigned)(s_key[i - 1] >> 32) - r_lo) >> shift);
+    for (int q = bp + 1; q <= b; ++q) s_start[q] = i;  // buckets (bp, b] start at slot i
+  }
+  const int b_last = (int)((r_hi - r_lo) >> shift);
+  for (int q = b_last + 1 + tid; q <= kYZBuckets + 1; q += kYZThreads) s_start[q] = nv;
+  __syncthreads();
   auto rank = [&](float dist) {
     const unsigned db = __float_as_uint(dist);
-    int pos = 0;
-    for (int b = P2; b >= 1; b >>= 1)
-      if (pos + b <= P2 && (unsigned)(s_key[pos + b - 1] >> 32) <= db) pos += b;
-    return pos;
+    if (db < r_lo) return 0;
+    if (db >= r_hi) return nv;
+    const int b = (int)((db - r_lo) >> shift);  // b < b_last + 1 <= kYZBuckets
+    int lo = s_start[b], hi = s_start[b + 1];
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((unsigned)(s_key[mid] >> 32) <= db) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
   };
   unsigned c0z = 0, c0yz = 0, visited = 0;
   auto visit = [&](int j) {
@@ -140,21 +164,28 @@ __global__ __launch_bounds__(kYZThreads) void ksg_yzcount_kernel(const float* __
     sz += s_hz[q];
     syz += s_hyz[q];
   }
-  s_part[0][tid] = sz;
-  s_part[1][tid] = syz;
-  __syncthreads();
-  if (tid == 0) {
-    unsigned az = 0, ayz = 0;
-    for (int t = 0; t < kYZThreads; ++t) {
-      const unsigned vz = s_part[0][t], vyz = s_part[1][t];
-      s_part[0][t] = az;
-      s_part[1][t] = ayz;
-      az += vz;
-      ayz += vyz;
+  // exclusive scan of the threads' chunk sums: inclusive within each wave by shuffles, then the
+  // totals of the lower waves
+  const int lane = tid & 63, wave = tid >> 6;
+  unsigned iz = sz, iyz = syz;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const unsigned tz = __shfl_up(iz, off, 64), tyz = __shfl_up(iyz, off, 64);
+    if (lane >= off) {
+      iz += tz;
+      iyz += tyz;
     }
   }
+  if (lane == 63) {
+    s_part[0][wave] = iz;
+    s_part[1][wave] = iyz;
+  }
   __syncthreads();
-  unsigned az = s_part[0][tid], ayz = s_part[1][tid];
+  unsigned az = iz - sz, ayz = iyz - syz;
+  for (int w = 0; w < wave; ++w) {
+    az += s_part[0][w];
+    ayz += s_part[1][w];
+  }
   for (int q = b0; q < b1; ++q) {
     az += s_hz[q];
     ayz += s_hyz[q];
