@@ -337,12 +337,18 @@ def _key_window_case(case):
         z = p.z.copy()
         z[:, 0] = np.sort(z[:, 0])
         return g.standard_normal((3, n)).astype(np.float32), p.y[:, 0], z, 4
-    # case 5: no Z (the key is Y; the count pass scans every row)
-    p = workloads.random_problem(1205, 500, 1, 1, 0, 4, kind="grid")
-    return g.integers(0, 5, size=(3, 500)).astype(np.float32), p.y[:, 0], None, 4
+    if case == 5:  # no Z (the key is Y; the count pass scans every row)
+        p = workloads.random_problem(1205, 500, 1, 1, 0, 4, kind="grid")
+        return g.integers(0, 5, size=(3, 500)).astype(np.float32), p.y[:, 0], None, 4
+    # case 6: every row repeated six times in all columns: the unpermuted problems have eps = 0
+    # at every row (all radii equal), the surrogates a mix of zero and positive radii
+    p = workloads.random_problem(1206, 60, 1, 1, 2, 4)
+    rep = np.repeat(np.arange(60), 6)
+    cands = np.repeat(g.standard_normal((3, 60)).astype(np.float32), 6, axis=1)
+    return cands, p.y[rep, 0], p.z[rep], 4
 
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(7))
 def test_grouped_key_window_edge_cases(lib, ctx, case):
     """Ties, constant and degenerate keys, short and ragged inputs: the key-ordered grouped
     search equals the oracle on every candidate and surrogate."""
