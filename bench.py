@@ -582,6 +582,9 @@ def main():
         "search": search,
         "autotune": {"group_size_k4_by_m": tuned["k<=4"] if tuned else None,
                      "seconds": round(t_tune, 3)},
+        "device": {k_: v_ for k_, v_ in ksg.device_props(0).items()
+                   if k_ in ("name", "arch", "cus", "clock_khz", "mem_clock_khz", "mem_bus_bits",
+                             "total_mem", "l2_bytes", "lds_per_cu")},
     }
 
     if args.copy_calibration:

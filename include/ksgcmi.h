@@ -72,6 +72,25 @@ const char* ksg_status_string(int status);
 /* Number of visible HIP devices (0 when none); never fails. */
 int ksg_device_count(void);
 
+/* What the HIP runtime reports for a device (the figures the roofline's peaks derive from). */
+typedef struct ksg_device_props {
+  char name[128];
+  char arch[64];         /* gcnArchName, e.g. "gfx950:sramecc+:xnack-" */
+  int32_t cus;           /* compute units */
+  int32_t clock_khz;     /* peak engine clock */
+  int32_t mem_clock_khz; /* peak memory clock */
+  int32_t mem_bus_bits;  /* memory bus width */
+  int64_t total_mem;     /* bytes */
+  int32_t l2_bytes;
+  int32_t lds_per_cu;    /* bytes of LDS per compute unit */
+  int32_t lds_per_block; /* bytes of LDS one work-group may use */
+  int32_t wave_size;
+} ksg_device_props;
+
+/* Fill *out for HIP device `device` (host call; no context needed).
+ * Errors: KSG_EINVAL (out NULL), KSG_ENODEV (no such device). */
+int ksg_device_props_get(int32_t device, ksg_device_props* out);
+
 /* Host utility (no device needed): harmonic numbers H_0..H_nmax (H_n = sum_{m<=n} 1/m, so
  * psi(n+1) = H_n - Euler's gamma) into the host array out[nmax+1], FP64, from a
  * double-double running sum.  These are the digamma values the estimator uses.

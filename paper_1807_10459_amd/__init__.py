@@ -15,6 +15,7 @@ from ._binding import (  # noqa: F401
     KsgError,
     Problem,
     ThresholdNet,
+    device_props,
     fdr_bh,
     maxstat_sequential,
     harmonic_table,

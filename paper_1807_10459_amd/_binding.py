@@ -40,6 +40,13 @@ class _MaxStat(C.Structure):
                 ("tau05", C.c_double), ("tau01", C.c_double)]
 
 
+class _DeviceProps(C.Structure):
+    _fields_ = [("name", C.c_char * 128), ("arch", C.c_char * 64), ("cus", C.c_int32), ("clock_khz", C.c_int32),
+                ("mem_clock_khz", C.c_int32), ("mem_bus_bits", C.c_int32), ("total_mem", C.c_int64),
+                ("l2_bytes", C.c_int32), ("lds_per_cu", C.c_int32), ("lds_per_block", C.c_int32),
+                ("wave_size", C.c_int32)]
+
+
 class _SelectOpts(C.Structure):
     _fields_ = [("k", C.c_int32), ("max_lag", C.c_int32), ("n_perm", C.c_int32),
                 ("omnibus", C.c_int32), ("alpha", C.c_double), ("perms", C.c_void_p),
@@ -74,6 +81,7 @@ def _load():
         "ksg_status_string": ([i32], C.c_char_p),
         "ksg_device_count": ([], i32),
         "ksg_harmonic_table": ([i64, vp], i32),
+        "ksg_device_props_get": ([i32, C.POINTER(_DeviceProps)], i32),
         "ksg_ctx_create": ([C.POINTER(vp), i32, vp], i32),
         "ksg_ctx_destroy": ([vp], None),
         "ksg_last_error": ([vp], C.c_char_p),
@@ -126,6 +134,18 @@ def harmonic_table(nmax: int) -> np.ndarray:
     st = lib.ksg_harmonic_table(nmax, out.ctypes.data)
     if st:
         raise KsgError(st, "ksg_harmonic_table")
+    return out
+
+
+def device_props(device: int = 0) -> dict:
+    """What the HIP runtime reports for a device (see ksg_device_props_get)."""
+    p = _DeviceProps()
+    st = lib.ksg_device_props_get(int(device), C.byref(p))
+    if st:
+        raise KsgError(st, "ksg_device_props_get")
+    out = {f: getattr(p, f) for f, _ in _DeviceProps._fields_}
+    out["name"] = p.name.decode(errors="replace")
+    out["arch"] = p.arch.decode(errors="replace")
     return out
 
 

@@ -150,6 +150,33 @@ extern "C" int ksg_device_count(void) {
   return n;
 }
 
+extern "C" int ksg_device_props_get(int32_t device, ksg_device_props* out) {
+  if (!out) return KSG_EINVAL;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return KSG_ENODEV;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    (void)hipGetLastError();
+    return KSG_ENODEV;
+  }
+  std::memset(out, 0, sizeof *out);
+  std::snprintf(out->name, sizeof out->name, "%s", prop.name);
+  std::snprintf(out->arch, sizeof out->arch, "%s", prop.gcnArchName);
+  out->cus = prop.multiProcessorCount;
+  out->clock_khz = prop.clockRate;
+  out->mem_clock_khz = prop.memoryClockRate;
+  out->mem_bus_bits = prop.memoryBusWidth;
+  out->total_mem = (int64_t)prop.totalGlobalMem;
+  out->l2_bytes = prop.l2CacheSize;
+  out->lds_per_cu = (int32_t)prop.maxSharedMemoryPerMultiProcessor;
+  out->lds_per_block = (int32_t)prop.sharedMemPerBlock;
+  out->wave_size = prop.warpSize;
+  return KSG_OK;
+}
+
 extern "C" int ksg_harmonic_table(int64_t nmax, double* out) {
   if (nmax < 0 || !out) return KSG_EINVAL;
   ksg_build_harmonic(nmax, out);

@@ -392,3 +392,16 @@ def test_valu_probe_classes(lib, ctx):
         assert 1e12 < r < 1.05 * 78.65e12, (kind, r)
     with pytest.raises(lib.KsgError):
         ctx.valu_probe(18)
+
+
+def test_device_props(lib):
+    """The runtime's figures for the device the roofline is priced on."""
+    import torch
+    p = lib.device_props(0)
+    tp = torch.cuda.get_device_properties(0)
+    assert p["cus"] == tp.multi_processor_count
+    assert p["arch"].startswith("gfx950")
+    assert p["wave_size"] == 64 and p["clock_khz"] > 0 and p["total_mem"] == tp.total_memory
+    print("device", p)
+    with pytest.raises(lib.KsgError):
+        lib.device_props(10 ** 6)
