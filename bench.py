@@ -88,6 +88,37 @@ def cpu_baseline(cand, y, perms, order, sample_per_m=2, workers=None, alg=1):
     return len(tasks) / wall, workers, desc, vals
 
 
+def kdtree_context(cand, y, perms, order, per_m=2):
+    """Context only (not the oracle, not parity): KSG with SciPy's k-d tree in FP64 on all host
+    threads, on the same sample of the step's CMIs as the oracle baseline: (CMI/s, threads)."""
+    from scipy.spatial import cKDTree
+    from oracle.harmonic import harmonic_table
+    h = harmonic_table(cand.shape[1])
+
+    def ksg_tree(x, z):
+        n = x.shape[0]
+        xz = np.concatenate([x[:, None], z], 1).astype(np.float64)
+        yz = np.concatenate([y[:, None], z], 1).astype(np.float64)
+        joint = np.concatenate([x[:, None], y[:, None], z], 1).astype(np.float64)
+        d, _ = cKDTree(joint).query(joint, k=K + 1, p=np.inf, workers=-1)
+        r = np.nextafter(d[:, K], 0)
+        cnt = [cKDTree(c).query_ball_point(c, r=r, p=np.inf, return_length=True, workers=-1) - 1
+               for c in (xz, yz, z.astype(np.float64))]
+        return h[K - 1] - (h[cnt[0]] + h[cnt[1]] - h[cnt[2]]).mean()
+
+    n_done = 0
+    t0 = time.perf_counter()
+    for m in FORCED_M:
+        z = np.stack([cand[c] for c in order[:m]], axis=1)
+        pool = [c for c in range(cand.shape[0]) if c not in order[:m]]
+        for s_ in range(per_m):
+            ci = (3 * s_ + m) % len(pool)
+            x = cand[pool[ci]] if s_ == 0 else cand[pool[ci]][perms[s_ - 1]]
+            ksg_tree(x, z)
+            n_done += 1
+    return n_done / (time.perf_counter() - t0), os.cpu_count()
+
+
 # ---------------------------------------------------------------------------------------------
 # Learned null: training set from seeded networks (seeds disjoint from the evaluation network)
 
@@ -608,6 +639,11 @@ def main():
         line["cpu_baseline"] = {"value": round(cps, 3), "unit": "CMI/s", "cores": cores, "kind": "oracle",
                                 "sample": desc}
         line["parity_spot_check_max_rel_err"] = worst
+        kps, threads = kdtree_context(cand_np, y_np, perms_np, order)
+        line["cpu_context"] = {"value": round(kps, 3), "unit": "CMI/s", "threads": threads,
+                               "kind": "SciPy cKDTree KSG in FP64 (context only: a tree search, not the "
+                                       "oracle and not FP32-exact)",
+                               "sample": "the same 16 CMIs as cpu_baseline"}
     line["steps_detail"] = {str(m): {"c_star_candidate": [c for c in range(25) if c not in order[:m]][r["c_star"]],
                                      "t_obs": round(r["t_obs"], 6), "pval": r["pval"]}
                             for m, r in results.items()}
