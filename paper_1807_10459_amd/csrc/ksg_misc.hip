@@ -186,18 +186,27 @@ __global__ __launch_bounds__(256) void interleave_kernel(const GroupDesc* __rest
       const unsigned r = (unsigned)sigma[row];
       return r < (unsigned)gd.n_pad ? (int)r : row;  // sigma is a permutation; never trust it blindly
     };
+    // one row per thread: its source row is looked up once and its G (and m + 1) values are
+    // gathered with independent loads
     float* xi = base + gd.xi_off;
-    for (int e = s0 * G * 4 + threadIdx.x; e < s1 * G * 4; e += 256) {
-      const int s = e / (G * 4), r = e - s * G * 4, g = r >> 2, u = r & 3;
-      xi[e] = base[gd.x_off[g] + src_row(s * 4 + u)];
-    }
-    if (gd.write_yz) {
-      const int W = gd.m + 1;
-      float* yzi = base + gd.yzi_off;
-      for (int e = s0 * W * 4 + threadIdx.x; e < s1 * W * 4; e += 256) {
-        const int s = e / (W * 4), r = e - s * W * 4, a = r >> 2, u = r & 3;
-        const uint32_t src = a == 0 ? gd.y_off : gd.z_off[a - 1];
-        yzi[e] = base[src + src_row(s * 4 + u)];
+    const int row = s0 * 4 + (int)threadIdx.x;  // 64 steps = 256 rows per block
+    if (row < s1 * 4) {
+      const int src = src_row(row);
+      const int s = row >> 2, u = row & 3;
+      float v[kGroupMax];
+#pragma unroll
+      for (int g = 0; g < kGroupMax; ++g)
+        if (g < G) v[g] = base[gd.x_off[g] + src];
+#pragma unroll
+      for (int g = 0; g < kGroupMax; ++g)
+        if (g < G) xi[(s * G + g) * 4 + u] = v[g];
+      if (gd.write_yz) {
+        const int W = gd.m + 1;
+        float* yzi = base + gd.yzi_off;
+        for (int a = 0; a < W; ++a) {
+          const uint32_t col = a == 0 ? gd.y_off : gd.z_off[a - 1];
+          yzi[(s * W + a) * 4 + u] = base[col + src];
+        }
       }
     }
   }
