@@ -116,7 +116,7 @@ typedef enum ksg_option {
                                0 = off, 8 or 16 = forced */
   KSG_OPT_USE_GRAPH = 3,    /* 1 (default): replay greedy steps from a captured hipGraph */
   KSG_OPT_TIMING = 4,       /* 1: time every search-kernel launch with HIP events (default 0) */
-  KSG_OPT_ALGORITHM = 5     /* KSG algorithm of every later estimate (default 1):
+  KSG_OPT_ALGORITHM = 5,    /* KSG algorithm of every later estimate (default 1):
                              * 1: eps_i = joint k-th neighbour distance, strict counts in XZ, YZ, Z,
                              *    I = H_{k-1} - <H_{n_xz} + H_{n_yz} - H_{n_z}>;
                              * 2: the k nearest neighbours (ties by the lower index) span a
@@ -127,6 +127,11 @@ typedef enum ksg_option {
                              *    counts_out then holds these counts (n_z = N-1 without Z), eps_out
                              *    the k-th neighbour's joint distance, local_out the pointwise values.
                              *    Problems are searched one by one (no grouping). */
+  KSG_OPT_WINDOWS = 6       /* 1 (default): single problems (not grouped) with k <= 4, N >= 2048,
+                             * no per-point outputs and an unpermuted Z column are searched with
+                             * their rows in the order of that column, each tile scanning only the
+                             * rows its radii and counts can reach (same results up to the order
+                             * of the FP64 sum); 0: brute force over all rows */
 } ksg_option;
 int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
 

@@ -234,6 +234,7 @@ class Context:
     OPT_USE_GRAPH = 3
     OPT_TIMING = 4
     OPT_ALGORITHM = 5
+    OPT_WINDOWS = 6
 
     def __init__(self, device: int = 0, stream=None):
         import torch

@@ -21,6 +21,7 @@ SOURCES = [
     "ksg_group_kp9_g16.hip",
     "ksg_yzcount.hip",
     "ksg_alg2.hip",
+    "ksg_window.hip",
     "ksg_misc.hip",
     "ksg_api.hip",
     "greedy.hip",

@@ -10,6 +10,7 @@ constexpr int kMaxDims = 16;
 constexpr int kTileQ = 256;       // queries per work item (4 waves x 64 lanes, one query per lane)
 constexpr int kPad = 64;          // column length is padded to a multiple of this with +inf
 constexpr int kMaxK = 16;
+constexpr int kWindowMinN = 2048;  // smallest N searched with key-ordered windows (single problems)
 
 // One CMI problem as the search kernel sees it.  Columns are ordered X..., Y..., Z...,
 // each padded with +inf rows up to n_pad.  128 + 64 bytes, 16-byte aligned.
@@ -27,7 +28,8 @@ struct alignas(16) ProbDesc {
   int32_t out_index;  // slot in the output array
   int32_t swap_xy;    // 1: X and Y were exchanged to reach a fast shape (count rows swap back)
   int32_t alg;        // KSG algorithm: 1 (joint radius, strict counts) or 2 (rectangles)
-  int32_t pad_[2];
+  int32_t key_col;    // key-ordered window search: the column (a Z column) the rows are sorted by
+  int32_t pad_;
 };
 
 // G problems that share Y (1-D), Z (m columns), N and k and differ in a 1-D X column.
@@ -87,6 +89,7 @@ struct PackJob {
   float* dst;
   int32_t n;
   int32_t n_pad;
+  const int32_t* order;  // nullptr, or: destination row r takes source row perm[order[r]] (order[r])
 };
 
 // Fast shapes are (dx, dy) in {(1,1), (1,2), (2,2)} with dz in [0, kFastMaxDz]; every
@@ -124,6 +127,11 @@ struct MaxStatOut {
 hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                              const double* d_htab, double* d_partials, int shape, int kp,
                              hipStream_t stream);
+// Key order of one column (sigma[rank] = row) and the key-ordered window search over the work
+// items of problems that all have D columns (k <= 4).
+hipError_t launch_window_rank(const float* key, int n, int n_pad, int32_t* sigma, hipStream_t stream);
+hipError_t launch_ksg_window(const ProbDesc* d_desc, const WorkItem* d_items, int n_items, const double* d_htab,
+                             double* d_partials, int D, unsigned long long* d_work, hipStream_t stream);
 // KSG algorithm 2 over the work items of problems that all have D columns.
 hipError_t launch_ksg_alg2(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                            const double* d_htab, double* d_partials, int D, int kp, hipStream_t stream);

@@ -249,6 +249,7 @@ extern "C" int ksg_ctx_set_option(ksg_ctx* c, int option, int64_t value) {
       c->group_size = (int)value;
       return KSG_OK;
     case KSG_OPT_USE_GRAPH: c->use_graph = value != 0; return KSG_OK;
+    case KSG_OPT_WINDOWS: c->use_windows = value != 0; return KSG_OK;
     case KSG_OPT_ALGORITHM:
       if (value != 1 && value != 2) return c->fail(KSG_EINVAL, "KSG algorithm must be 1 or 2");
       c->algorithm = (int)value;
@@ -256,8 +257,8 @@ extern "C" int ksg_ctx_set_option(ksg_ctx* c, int option, int64_t value) {
     case KSG_OPT_TIMING:
       c->timing = value != 0;
       if (c->timing && !c->d_work) {
-        if (hipMalloc(&c->d_work, 5 * sizeof(unsigned long long)) != hipSuccess ||
-            hipMemset(c->d_work, 0, 5 * sizeof(unsigned long long)) != hipSuccess) {
+        if (hipMalloc(&c->d_work, 6 * sizeof(unsigned long long)) != hipSuccess ||
+            hipMemset(c->d_work, 0, 6 * sizeof(unsigned long long)) != hipSuccess) {
           (void)hipGetLastError();
           c->d_work = nullptr;
           c->timing = false;
@@ -379,17 +380,45 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     }
   }
 
+  // ---- key-ordered windows: ungrouped problems (k <= 4, no per-point outputs, N large enough)
+  // that share an unpermuted Z column are searched in the order of that column ----
+  std::vector<int> win_of(np, -1), win_key(np, -1);  // window set, key column (original index)
+  std::vector<std::pair<const float*, int64_t>> wsets;  // (key column, N)
+  if (algorithm == 1 && use_windows) {
+    std::map<std::pair<const float*, int64_t>, int> by_key;
+    for (int i = 0; i < np; ++i) {
+      const Problem& p = probs[i];
+      if (group_of[i] >= 0 || p.k + 1 > 5 || p.n < kWindowMinN || p.dz < 1) continue;
+      if (p.eps_out || p.counts_out || p.local_out) continue;
+      int a_key = -1;
+      for (int a = p.dx + p.dy; a < p.dx + p.dy + p.dz && a_key < 0; ++a)
+        if (!p.perm[a]) a_key = a;
+      if (a_key < 0) continue;
+      const auto kk = std::make_pair(p.col[a_key], p.n);
+      auto it = by_key.find(kk);
+      if (it == by_key.end()) {
+        it = by_key.emplace(kk, (int)wsets.size()).first;
+        wsets.push_back(kk);
+      }
+      win_of[i] = it->second;
+      win_key[i] = a_key;
+    }
+  }
+
   // ---- column pool: pack every column that is not already a padded device column ----
-  // Grouped problems address all their columns through one pool, so they always pack.
+  // Grouped problems address all their columns through one pool, so they always pack; so do
+  // window problems, in their set's key order.
   struct Key {
     const float* src;
     const int32_t* perm;
     int64_t n;
-    bool operator==(const Key& o) const { return src == o.src && perm == o.perm && n == o.n; }
+    int wset;
+    bool operator==(const Key& o) const { return src == o.src && perm == o.perm && n == o.n && wset == o.wset; }
   };
   struct KeyHash {
     size_t operator()(const Key& k) const {
-      return std::hash<const void*>()(k.src) * 31u ^ std::hash<const void*>()(k.perm) ^ (size_t)k.n;
+      return std::hash<const void*>()(k.src) * 31u ^ std::hash<const void*>()(k.perm) ^ (size_t)k.n ^
+             ((size_t)(k.wset + 1) << 20);
     }
   };
   std::unordered_map<Key, int64_t, KeyHash> slot;
@@ -403,11 +432,11 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     const int64_t n_pad = round_up(p.n, kPad);
     max_pad = std::max<int>(max_pad, (int)n_pad);
     for (int a = 0; a < D; ++a) {
-      if (p.padded[a] && !p.perm[a] && group_of[i] < 0) {
+      if (p.padded[a] && !p.perm[a] && group_of[i] < 0 && win_of[i] < 0) {
         col_off[i][a] = -1;  // used in place
         continue;
       }
-      Key key{p.col[a], p.perm[a], p.n};
+      Key key{p.col[a], p.perm[a], p.n, win_of[i]};
       auto it = slot.find(key);
       if (it == slot.end()) {
         it = slot.emplace(key, pool_floats).first;
@@ -417,11 +446,19 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
         j.dst = reinterpret_cast<float*>(pool_floats);  // offset for now
         j.n = (int)p.n;
         j.n_pad = (int)n_pad;
+        // window set index + 1 for now (the key order's address is known after the pool is reserved)
+        j.order = win_of[i] >= 0 ? reinterpret_cast<const int32_t*>((intptr_t)(win_of[i] + 1)) : nullptr;
         jobs.push_back(j);
         pool_floats += n_pad;
       }
       col_off[i][a] = it->second;
     }
+  }
+  // key orders of the window sets (int32, n_pad entries each) follow the packed columns
+  std::vector<int64_t> wsigma_off(wsets.size());
+  for (size_t w = 0; w < wsets.size(); ++w) {
+    wsigma_off[w] = pool_floats;
+    pool_floats += round_up(wsets[w].second, kPad);
   }
   // Interleaved blocks of the groups follow the packed columns in the same pool.
   std::vector<int64_t> xi_off(groups.size()), yzi_off(groups.size()), sigma_off(groups.size());
@@ -454,7 +491,10 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   st = reserve(pool, sizeof(float) * std::max<int64_t>(pool_floats, 1), "column pool");
   if (st) return st;
   float* pool_base = static_cast<float*>(pool.ptr);
-  for (PackJob& j : jobs) j.dst = pool_base + reinterpret_cast<int64_t>(j.dst);
+  for (PackJob& j : jobs) {
+    j.dst = pool_base + reinterpret_cast<int64_t>(j.dst);
+    if (j.order) j.order = reinterpret_cast<const int32_t*>(pool_base + wsigma_off[(intptr_t)j.order - 1]);
+  }
 
   auto cost = [&](int i) {
     const Problem& p = probs[i];
@@ -508,10 +548,14 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     d.out_index = p.out_index;
     d.swap_xy = swap ? 1 : 0;
     d.alg = algorithm;
+    d.key_col = win_key[i];  // a Z column: its index is the same in the canonical order
     if (group_of[i] >= 0) {
       const int gi = group_of[i];
       const int g = (int)(std::find(groups[gi].begin(), groups[gi].end(), i) - groups[gi].begin());
       d.part_base = group_part[gi] + g * d.n_tiles;
+    } else if (win_of[i] >= 0) {
+      d.part_base = part;
+      part += d.n_tiles;
     } else {
       d.part_base = part;
       part += d.n_tiles;
@@ -547,9 +591,25 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   } else {
     std::vector<Unit> units;
     for (int r = 0; r < np; ++r)
-      if (group_of[order[r]] < 0) units.push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
+      if (group_of[order[r]] < 0 && win_of[order[r]] < 0) units.push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
     items = order_items(units);
   }
+  // window problems: one launch per column count, after the other ungrouped items
+  std::vector<Segment> wsegments;
+  {
+    std::map<int, std::vector<Unit>> by_d;
+    for (int r = 0; r < np; ++r) {
+      const Problem& p = probs[order[r]];
+      if (win_of[order[r]] >= 0) by_d[p.dx + p.dy + p.dz].push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
+    }
+    for (auto& kv : by_d) {
+      std::vector<WorkItem> seg = order_items(kv.second);
+      wsegments.push_back(Segment{kv.first, 5, (int)items.size(), (int)seg.size()});
+      items.insert(items.end(), seg.begin(), seg.end());
+    }
+  }
+  const int n_plain_items = algorithm == 2 ? (int)items.size()
+                                           : (wsegments.empty() ? (int)items.size() : wsegments[0].off);
 
   // ---- groups: descriptors, launch chunks, Y/Z count descriptors, work items ----
   // Groups of one (m, G, KP) class run as chunks of consecutive groups, each chunk three
@@ -706,6 +766,9 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
 
   // ---- pack, optional finite check, search, finalise ----
   if (check_finite) KSG_HIP(this, hipMemsetAsync(d_flag, 0, sizeof(int), stream));
+  for (size_t w = 0; w < wsets.size(); ++w)  // key orders first: the pack step reads them
+    KSG_HIP(this, launch_window_rank(wsets[w].first, (int)wsets[w].second, (int)round_up(wsets[w].second, kPad),
+                                     reinterpret_cast<int32_t*>(pool_base + wsigma_off[w]), stream));
   if (!jobs.empty()) {
     KSG_HIP(this, launch_pack((const PackJob*)this->jobs.ptr, (int)jobs.size(), max_pad, d_flag, stream));
   }
@@ -776,18 +839,27 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
                                     (double*)partials.ptr, g.D, g.kp, stream));
       if ((st = span_end(3))) return st;
     }
-  } else if (!items.empty()) {
-    const int shape = common_shape;
-    if ((st = span_begin())) return st;
-    KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items, (int)items.size(),
-                                    (const double*)htab.ptr, (double*)partials.ptr, shape, kp, stream));
-    if ((st = span_end(3))) return st;
+  } else {
+    if (n_plain_items > 0) {
+      const int shape = common_shape;
+      if ((st = span_begin())) return st;
+      KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items, n_plain_items, (const double*)htab.ptr,
+                                      (double*)partials.ptr, shape, kp, stream));
+      if ((st = span_end(3))) return st;
+    }
+    for (const Segment& g : wsegments) {
+      if ((st = span_begin())) return st;
+      KSG_HIP(this, launch_ksg_window((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
+                                      (double*)partials.ptr, g.D, d_w, stream));
+      if ((st = span_end(3))) return st;
+    }
   }
   if (timing) {
     KSG_HIP(this, hipEventRecord(t1, stream));
     timed.emplace_back(t0, t1);
+    // window problems are counted by their kernel over the work executed (ksg_take_timing)
     for (int i = 0; i < np; ++i)
-      if (group_of[i] < 0) timed_ops += algorithmic_ops(probs[i], 1);
+      if (group_of[i] < 0 && win_of[i] < 0) timed_ops += algorithmic_ops(probs[i], 1);
   }
   KSG_HIP(this, launch_finalize((const ProbDesc*)desc.ptr, np, (const double*)partials.ptr,
                                 (const double*)htab.ptr, d_out, stream));
@@ -976,14 +1048,15 @@ extern "C" int ksg_take_timing(ksg_ctx* c, double* ms, int64_t* launches, double
     c->event_pool.push_back(sp.a);
     c->event_pool.push_back(sp.b);
   }
-  unsigned long long w[5] = {0, 0, 0, 0, 0};
+  unsigned long long w[6] = {0, 0, 0, 0, 0, 0};
   if (c->d_work) {
     KSG_HIP(c, hipMemcpy(w, c->d_work, sizeof w, hipMemcpyDeviceToHost));
     KSG_HIP(c, hipMemset(c->d_work, 0, sizeof w));
   }
   for (int i = 0; i < 5; ++i) c->last_work[i] = w[i];
+  // w[5]: operations / 256 executed by the key-ordered window search (single-problem kind)
   const double kops[4] = {256.0 * (3.0 * (double)w[0] + (double)w[2]), (double)w[3],
-                          256.0 * (3.0 * (double)w[1] + (double)w[4]), c->timed_ops};
+                          256.0 * (3.0 * (double)w[1] + (double)w[4]), c->timed_ops + 256.0 * (double)w[5]};
   for (int i = 0; i < 4; ++i) {
     c->last_kernel_ms[i] = kms[i];
     c->last_kernel_ops[i] = kops[i];

@@ -41,8 +41,9 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackJob* __restrict__ j
       const int i = base + r * 256 + threadIdx.x;
       if (i < job.n) {
         int src = i;
+        if (job.order) src = job.order[i];  // a permutation of [0, n) written by window_rank_kernel
         if (job.perm) {
-          src = job.perm[i];
+          src = job.perm[src];
           if ((unsigned)src >= (unsigned)job.n) {
             bad = true;
             job.dst[i] = NAN;

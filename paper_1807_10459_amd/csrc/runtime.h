@@ -55,6 +55,7 @@ struct ksg_ctx {
   bool check_finite = true;
   int group_size = -1;           // -1: tuned per conditioning dimension, 0: no grouping, 8 or 16
   int algorithm = 1;             // KSG algorithm of every estimate: 1 or 2
+  bool use_windows = true;       // key-ordered window search for eligible single problems
   int tuned_g[2][15] = {{0}};    // [k <= 4 ? 0 : 1][m]: group size picked by the autotuner (0 = default)
   bool use_graph = true;
 

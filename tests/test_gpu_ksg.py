@@ -405,3 +405,30 @@ def test_device_props(lib):
     print("device", p)
     with pytest.raises(lib.KsgError):
         lib.device_props(10 ** 6)
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_window_search_matches_oracle(lib, ctx, case):
+    """Single problems searched in key order with windows (N >= 2048, k <= 4, a Z column):
+    every estimate equals the oracle's, and the brute-force search's up to the FP64 summation
+    order.  Batches of multi-column X share Y and Z (as the omnibus test's do); single problems
+    of 1-D X are not grouped and take the same path; grid data put many rows on each key."""
+    dims, kind, n_perm, k = [((3, 1, 2), "gaussian", 3, 4), ((1, 4, 3), "gaussian", 2, 3),
+                             ((1, 1, 2), "gaussian", 0, 4), ((2, 1, 1), "grid", 2, 4),
+                             ((1, 2, 5), "unit12", 1, 1)][case]
+    n = 2400 + 97 * case
+    p = workloads.random_problem(1400 + case, n, *dims, k, kind=kind)
+    perms = workloads.permutations(n, max(n_perm, 1), seed=1500 + case)
+    xd, yd, zd = soa(p.x), soa(p.y), soa(p.z)
+    dp = dev(perms)
+    probs = [lib.Problem(xd, yd, zd, k)] + [lib.Problem(xd, yd, zd, k, perm_x=dp[q]) for q in range(n_perm)]
+    got = {}
+    for w in (1, 0):
+        ctx.set_option(ctx.OPT_WINDOWS, w)
+        got[w] = ctx.cmi_batch(probs).cpu().numpy()
+    ctx.set_option(ctx.OPT_WINDOWS, 1)
+    assert np.max(np.abs(got[1] - got[0])) <= _sum_order_bound(n)
+    for q in range(n_perm + 1):
+        xs = p.x if q == 0 else p.x[perms[q - 1]]
+        ref = ksg_cmi(xs, p.y, p.z, k)
+        assert abs(got[1][q] - ref) <= tol(ref), (case, q)
