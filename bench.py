@@ -333,6 +333,7 @@ def omnibus_bench(ksg, args):
     net = workloads.logistic_network(seed=3)
     data = torch.from_numpy(net.data).cuda()
     ctx = ksg.Context(0)
+    ctx.set_option(ctx.OPT_WINDOWS, 0 if args.no_windows else 1)
     cand, y = ctx.embed(data, target=0, max_lag=MAX_LAG)
     N = y.shape[0]
     idx = [v * MAX_LAG + lag - 1 for (v, lag) in OMNIBUS_PARENTS]
@@ -383,7 +384,8 @@ def omnibus_bench(ksg, args):
                      "peak": round(PEAK_VALU / 1e12, 3), "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_VALU, 4), "traffic": None,
                      "frac_4cycle_class": round(achieved / PEAK_VALU_4CYCLE, 4),
-                     "kernel": KERNEL_NAMES["single"], "kernel_ms_per_launch": round(ms / nl, 3),
+                     "kernel": KERNEL_NAMES["single"] if args.no_windows else KERNEL_NAMES["window"],
+                     "kernel_ms_per_launch": round(ms / nl, 3),
                      "launches": nl, "ops_per_launch": ops / nl},
         "omnibus_cmi": float(res[0]),
         "omnibus_pval": float(np.mean(res[1:] >= res[0])),
@@ -408,6 +410,8 @@ KERNEL_NAMES = {"radius": "ksg_group_radius_kernel (k-NN radius of each problem 
                             "rank histogram over the sorted radii)",
                 "x_count": "ksg_group_xcount_kernel (n_XZ of each problem of a group, digamma partial sums)",
                 "single": "ksg_batch_kernel (brute-force radius, counts and digamma partial sums)",
+                "window": "ksg_window_kernel (rows in key order, radius and counts within each tile's "
+                          "key window; operations counted over the pairs visited)",
                 "alg2": "ksg_alg2_kernel (KSG algorithm 2: indexed top-k, neighbour rectangles, "
                         "rectangle counts and partial sums)"}
 
@@ -439,6 +443,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--algorithm", type=int, default=1, choices=[1, 2],
                     help="KSG algorithm of the estimates (2: neighbour rectangles, searched one by one)")
+    ap.add_argument("--no-windows", action="store_true",
+                    help="search ungrouped problems by brute force over all rows (no key-ordered windows)")
     ap.add_argument("--group-size", type=int, default=-1,
                     help="problems searched together (-1 tuned, 0 off, 8, 16)")
     ap.add_argument("--workload", default="ar2", choices=["ar2", "c4", "modes", "omnibus"],
@@ -536,6 +542,7 @@ def main():
     t_tune = time.perf_counter() - t_tune
     ctx.set_option(ctx.OPT_GROUP_SIZE, args.group_size)
     ctx.set_option(ctx.OPT_ALGORITHM, args.algorithm)
+    ctx.set_option(ctx.OPT_WINDOWS, 0 if args.no_windows else 1)
     tables = {m: torch.empty((25 - m, N_PERM + 1), dtype=torch.float64, device="cuda") for m in FORCED_M}
 
     def step():
