@@ -158,9 +158,11 @@ int ksg_valu_probe(ksg_ctx* ctx, int32_t kind, int32_t iters, double* lane_ops_p
  * digamma sums, finalisation excluded) summed over all search phases since the last call, in
  * milliseconds, with their count and algorithmic operation count.  Problems searched alone
  * count N(N-1)(4D+2) (per ordered pair D subtractions, D-1 maxima and 1 compare for the
- * radius, the same plus 3 compares for the counts).  Problems searched in groups that share
- * Y and Z are counted on the device over the work executed (key windows and exact skips
- * decide which reference steps run): the shared Y/Z distances once per pair of an executed
+ * radius, the same plus 3 compares for the counts); with KSG_OPT_WINDOWS, the same per pair
+ * over the pairs that each wave's scan visits (padding lanes included).  Problems searched
+ * in groups that share Y and Z are counted on the device over the work executed (key
+ * windows and exact skips decide which reference steps run): the shared Y/Z distances once
+ * per pair of an executed
  * step (2m+2 for the radius, 2m for the X counts), 3 operations per pair for each problem's
  * radius and X count steps, and for the Y/Z counts, per visited reference, its d^Z and d^YZ
  * (2m+1) plus one compare per binary-search level for each of the two ranks.
@@ -175,9 +177,10 @@ int ksg_take_timing(ksg_ctx* ctx, double* ms, int64_t* launches, double* ops);
 int ksg_last_work(ksg_ctx* ctx, uint64_t* counters);
 
 /* Per-kernel split of the last ksg_take_timing (host arrays of 4, in the order: grouped
- * radius kernel, Y/Z count kernel, X count kernel, single-problem search kernel): device
- * milliseconds (each launch timed by its own pair of events), algorithmic operations (as
- * counted for ksg_take_timing) and launch counts.  Errors: KSG_EINVAL. */
+ * radius kernel, Y/Z count kernel, X count kernel, single-problem search kernels (brute force
+ * and key-ordered windows together)): device milliseconds (each launch timed by its own pair
+ * of events), algorithmic operations (as counted for ksg_take_timing) and launch counts.
+ * Errors: KSG_EINVAL. */
 int ksg_last_kernels(ksg_ctx* ctx, double* ms, double* ops, int64_t* launches);
 
 /* ---------------------------------------------------------------------------

@@ -432,3 +432,61 @@ def test_window_search_matches_oracle(lib, ctx, case):
         xs = p.x if q == 0 else p.x[perms[q - 1]]
         ref = ksg_cmi(xs, p.y, p.z, k)
         assert abs(got[1][q] - ref) <= tol(ref), (case, q)
+
+
+def _degenerate_key_case(case):
+    """Problems whose key column (Z_1) defeats or stresses the windows."""
+    if case == 0:  # every key equal: every row lies in every window (N at the window threshold)
+        p = workloads.random_problem(1600, 2048, 2, 1, 2, 4)
+        p.z[:, 0] = 0.5
+    elif case == 1:  # a few keys far out: windows end at large gaps on both sides
+        p = workloads.random_problem(1601, 2300, 1, 2, 2, 4)
+        g = workloads.rng(1602)
+        rows = g.choice(2300, size=9, replace=False)
+        p.z[rows, 0] = np.float32(1e30) * np.sign(g.standard_normal(9)).astype(np.float32)
+    elif case == 2:  # signed zeros and denormals among the keys (bit order differs from value order at 0)
+        p = workloads.random_problem(1603, 2200, 3, 1, 1, 3, kind="grid")
+        g = workloads.rng(1604)
+        p.z[:, 0] = np.where(g.random(2200) < 0.5, np.float32(-0.0), np.float32(0.0))
+        rows = g.choice(2200, size=40, replace=False)
+        p.z[rows, 0] = np.float32(1e-40) * g.integers(-3, 4, size=40).astype(np.float32)
+    else:  # wide Z with k = 2
+        p = workloads.random_problem(1605, 2500, 2, 2, 10, 2)
+    p.z = np.ascontiguousarray(p.z.astype(np.float32))
+    return p
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_window_search_degenerate_keys(lib, ctx, case):
+    """Key-ordered windows on tied, far-out, signed-zero and denormal keys: estimates equal the
+    oracle's and the brute-force search's (FP64 summation order aside); the window path runs
+    (its operation count, over the pairs it visits, is at most the brute force's)."""
+    p = _degenerate_key_case(case)
+    n, (dx, dy, dz) = p.n, p.dims
+    perms = workloads.permutations(n, 2, seed=1610 + case)
+    xd, yd, zd = soa(p.x), soa(p.y), soa(p.z)
+    dp = dev(perms)
+    probs = [lib.Problem(xd, yd, zd, p.k)] + [lib.Problem(xd, yd, zd, p.k, perm_x=dp[q]) for q in range(2)]
+    got, ops = {}, {}
+    ctx.set_option(ctx.OPT_TIMING, 1)
+    try:
+        for w in (1, 0):
+            ctx.set_option(ctx.OPT_WINDOWS, w)
+            ctx.take_timing()
+            got[w] = ctx.cmi_batch(probs).cpu().numpy()
+            ops[w] = ctx.take_timing()[2]
+    finally:
+        ctx.set_option(ctx.OPT_WINDOWS, 1)
+        ctx.set_option(ctx.OPT_TIMING, 0)
+    brute = 3 * n * (n - 1) * (4 * (dx + dy + dz) + 2)
+    assert ops[0] == pytest.approx(brute, rel=1e-12)
+    assert 0 < ops[1] <= brute * 1.05, (ops[1], brute)
+    if case == 0:
+        assert ops[1] > 0.9 * brute  # no window can exclude a row
+    else:
+        assert ops[1] < 0.9 * brute
+    assert np.max(np.abs(got[1] - got[0])) <= _sum_order_bound(n)
+    for q in range(3):
+        xs = p.x if q == 0 else p.x[perms[q - 1]]
+        ref = ksg_cmi(xs, p.y, p.z, p.k)
+        assert abs(got[1][q] - ref) <= tol(ref), (case, q)
