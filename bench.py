@@ -397,6 +397,7 @@ def omnibus_bench(ksg, args):
         ref = ksg_cmi(xs_np, y_np, zs_np, K)
         dt = time.perf_counter() - t1
         line["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "CMI/s", "cores": 1, "kind": "oracle",
+                                "cpu_model": _cpu_model(),
                                 "sample": "the original (unpermuted) omnibus CMI, one process"}
         line["parity_spot_check_abs_err"] = abs(float(res[0]) - ref)
     ctx.close()
@@ -414,6 +415,105 @@ KERNEL_NAMES = {"radius": "ksg_group_radius_kernel (k-NN radius of each problem 
                           "key window; operations counted over the pairs visited)",
                 "alg2": "ksg_alg2_kernel (KSG algorithm 2: indexed top-k, neighbour rectangles, "
                         "rectangle counts and partial sums)"}
+
+
+def _cpu_model():
+    """The host CPU's model name (Linux), for the CPU baseline's record."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def uneven_bench(ksg, args):
+    """64 independent problems of uneven size and shape (N log-uniform in [2000, 50000], d_x and
+    d_y in 1..2, d_z in 0..10, k in {4, 8}; Gaussian with random correlations): one batched
+    launch set per step.  Problems with k <= 4, N >= 2048 and a Z column run the key-ordered
+    window search, the rest the brute-force kernels compiled per shape or width."""
+    import torch
+    import workloads
+
+    def soa(pts):  # row-major [N][d] -> device [d][N] (None for d == 0)
+        return torch.from_numpy(np.ascontiguousarray(pts.T)).cuda() if pts.shape[1] else None
+
+    probs, _ = workloads.uneven_batch(seed=2)
+    ctx = ksg.Context(0)
+    ctx.set_option(ctx.OPT_WINDOWS, 0 if args.no_windows else 1)
+    cols = [(soa(p.x), soa(p.y), soa(p.z)) for p in probs]
+    batch = [ksg.Problem(x, y, z, p.k) for (x, y, z), p in zip(cols, probs)]
+    for _ in range(args.warmup):
+        ctx.cmi_batch(batch)
+    torch.cuda.synchronize()
+    ctx.set_option(ctx.OPT_TIMING, 1)
+    ctx.take_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = ctx.cmi_batch(batch)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.take_timing()
+    kern = ctx.last_kernels()
+    ctx.set_option(ctx.OPT_TIMING, 0)
+    ms, ops, nl = kern["single"]
+    achieved = ops / (ms * 1e-3)
+    res = out.cpu().numpy()
+    brute = [p.n * (p.n - 1) * (4 * sum(p.dims) + 2) for p in probs]
+    n_win = sum(1 for p in probs if p.k <= 4 and p.n >= 2048 and p.dims[2] >= 1)
+    line = {
+        "metric": "CMI estimates/sec (64-problem uneven batch, N in [2000, 50000], k in {4, 8})",
+        "value": round(len(probs) * args.steps / wall, 2),
+        "unit": "CMI/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * wall / args.steps, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "dtype_note": "FP32 differences, maxima and compares; FP64 only in the digamma sums",
+        "data": "synthetic",
+        "config": {"workload": f"64 Gaussian problems, N log-uniform in [2000, 50000] (sum {sum(p.n for p in probs)}), "
+                               f"d_x, d_y in 1..2, d_z in 0..10, k in {{4, 8}}; {n_win} searched with key-ordered "
+                               f"windows" + (" (off)" if args.no_windows else "")},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
+                     "peak": round(PEAK_VALU / 1e12, 3), "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_VALU, 4), "traffic": None,
+                     "frac_4cycle_class": round(achieved / PEAK_VALU_4CYCLE, 4),
+                     "kernel": "single-problem search kernels (brute force per shape or width, and "
+                               "the key-ordered window search; operations over the pairs each visits)",
+                     "kernel_ms_per_step": round(ms / args.steps, 3),
+                     "launches_per_step": nl / args.steps, "ops_per_step": ops / args.steps,
+                     "brute_force_ops_per_step": float(sum(brute))},
+    }
+    if not args.no_cpu_baseline:
+        from oracle.ksg import ksg_cmi
+        order = sorted(range(len(probs)), key=lambda i: probs[i].n)
+        done, sample_ops, worst = [], 0.0, 0.0
+        t1 = time.perf_counter()
+        for i in order:  # smallest problems first, until about 15 s of oracle time
+            p = probs[i]
+            ref = ksg_cmi(p.x, p.y, p.z, p.k)
+            worst = max(worst, abs(float(res[i]) - ref) / max(1.0, abs(ref)))
+            done.append(i)
+            sample_ops += brute[i]
+            if time.perf_counter() - t1 > 15.0:
+                break
+        dt = time.perf_counter() - t1
+        # the sample's brute-force operation rate, priced at the batch's mean work per CMI
+        cps = (sample_ops / dt) / (sum(brute) / len(probs))
+        line["cpu_baseline"] = {"value": round(cps, 4), "unit": "CMI/s", "cores": 1, "kind": "oracle",
+                                "cpu_model": _cpu_model(),
+                                "sample": f"the {len(done)} smallest problems (N {probs[done[0]].n}.."
+                                          f"{probs[done[-1]].n}), one process, {dt:.1f} s; rate scaled by "
+                                          f"the batch's mean brute-force operations per CMI"}
+        line["parity_spot_check_max_rel_err"] = worst
+    ctx.close()
+    return line
 
 
 def _kernel_source_hash():
@@ -447,7 +547,7 @@ def main():
                     help="search ungrouped problems by brute force over all rows (no key-ordered windows)")
     ap.add_argument("--group-size", type=int, default=-1,
                     help="problems searched together (-1 tuned, 0 off, 8, 16)")
-    ap.add_argument("--workload", default="ar2", choices=["ar2", "c4", "modes", "omnibus"],
+    ap.add_argument("--workload", default="ar2", choices=["ar2", "c4", "modes", "omnibus", "uneven"],
                     help="ar2: CMI/s on the AR(2) forced path (default); c4: learned vs plain null")
     ap.add_argument("--targets", default=None, help="c4: comma-separated targets (default all 20)")
     ap.add_argument("--dataset", default=None, help="c4: load the training set from this npz")
@@ -519,6 +619,11 @@ def main():
 
     if args.workload == "omnibus":
         line = omnibus_bench(ksg, args)
+        print(json.dumps(line))
+        return
+
+    if args.workload == "uneven":
+        line = uneven_bench(ksg, args)
         print(json.dumps(line))
         return
 
@@ -644,7 +749,7 @@ def main():
             g = float(tables[m][ci, p].cpu())
             worst = max(worst, abs(g - v) / max(1.0, abs(v)))
         line["cpu_baseline"] = {"value": round(cps, 3), "unit": "CMI/s", "cores": cores, "kind": "oracle",
-                                "sample": desc}
+                                "cpu_model": _cpu_model(), "sample": desc}
         line["parity_spot_check_max_rel_err"] = worst
         kps, threads = kdtree_context(cand_np, y_np, perms_np, order)
         line["cpu_context"] = {"value": round(kps, 3), "unit": "CMI/s", "threads": threads,

@@ -114,7 +114,9 @@ typedef enum ksg_option {
   KSG_OPT_GROUP_SIZE = 2,   /* problems searched together when they share Y, Z, N and k and
                                have 1-D X: -1 (default) = autotuned per conditioning dimension,
                                0 = off, 8 or 16 = forced */
-  KSG_OPT_USE_GRAPH = 3,    /* 1 (default): replay greedy steps from a captured hipGraph */
+  KSG_OPT_USE_GRAPH = 3,    /* accepted, no effect: steps are launched directly on the stream (a
+                             * greedy step is 6-8 launches around kernels of milliseconds, so
+                             * launch overhead is below 0.1%); no hipGraph is captured */
   KSG_OPT_TIMING = 4,       /* 1: time every search-kernel launch with HIP events (default 0) */
   KSG_OPT_ALGORITHM = 5,    /* KSG algorithm of every later estimate (default 1):
                              * 1: eps_i = joint k-th neighbour distance, strict counts in XZ, YZ, Z,

@@ -57,7 +57,7 @@ struct ksg_ctx {
   int algorithm = 1;             // KSG algorithm of every estimate: 1 or 2
   bool use_windows = true;       // key-ordered window search for eligible single problems
   int tuned_g[2][15] = {{0}};    // [k <= 4 ? 0 : 1][m]: group size picked by the autotuner (0 = default)
-  bool use_graph = true;
+  bool use_graph = true;         // KSG_OPT_USE_GRAPH: recorded only (no graph capture)
 
   ksg::DevBuf htab, pool, desc, items, partials, jobs, tmp, embed, cmi, aux, feat;
   ksg::DevBuf ebuf, tbuf;  // grouped search: radii E (FP32) and Y/Z count terms T (FP64)

@@ -490,3 +490,28 @@ def test_window_search_degenerate_keys(lib, ctx, case):
         xs = p.x if q == 0 else p.x[perms[q - 1]]
         ref = ksg_cmi(xs, p.y, p.z, p.k)
         assert abs(got[1][q] - ref) <= tol(ref), (case, q)
+
+
+def test_uneven_batch_windows_match_brute_force(lib, ctx):
+    """The 64-problem uneven batch without per-point outputs (so that the problems with k <= 4,
+    N >= 2048 and a Z column take the key-ordered window search, in the launch configuration
+    that the uneven-batch benchmark times): every estimate equals the brute-force search's up
+    to the FP64 summation order, and the smallest problems equal the oracle's."""
+    probs, _ = workloads.uneven_batch(seed=2)
+    batch = [lib.Problem(soa(p.x), soa(p.y), soa(p.z), p.k) for p in probs]
+    got = {}
+    try:
+        for w in (1, 0):
+            ctx.set_option(ctx.OPT_WINDOWS, w)
+            got[w] = ctx.cmi_batch(batch).cpu().numpy()
+    finally:
+        ctx.set_option(ctx.OPT_WINDOWS, 1)
+    n_win = 0
+    for i, p in enumerate(probs):
+        assert abs(got[1][i] - got[0][i]) <= _sum_order_bound(p.n), i
+        n_win += p.k <= 4 and p.n >= 2048 and p.dims[2] >= 1
+    assert n_win >= 20
+    for i in sorted(range(len(probs)), key=lambda i: probs[i].n)[:4]:
+        p = probs[i]
+        ref = ksg_cmi(p.x, p.y, p.z, p.k)
+        assert abs(got[1][i] - ref) <= tol(ref), i
