@@ -695,7 +695,8 @@ def main():
         "frac": round(achieved / PEAK_VALU, 4),
         "frac_4cycle_class": round(achieved / PEAK_VALU_4CYCLE, 4),
         "traffic": _traffic_record(dom),
-        "kernel": KERNEL_NAMES["alg2"] if args.algorithm == 2 else KERNEL_NAMES[dom],
+        "kernel": KERNEL_NAMES["alg2"] if args.algorithm == 2 else
+                  KERNEL_NAMES["window" if dom == "single" and not args.no_windows else dom],
         "kernel_ms_per_launch": round(d_ms / d_n, 3),
         "launches": d_n,
         "ops_per_launch": d_ops / d_n,
