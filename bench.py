@@ -455,11 +455,13 @@ def uneven_bench(ksg, args):
         out = ctx.cmi_batch(batch)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ctx.take_timing()
+    # the search span of each step (first launch to last, the launches running side by side
+    # on several streams) and the per-launch durations summed
+    span_ms, _, ops = ctx.take_timing()
     kern = ctx.last_kernels()
     ctx.set_option(ctx.OPT_TIMING, 0)
-    ms, ops, nl = kern["single"]
-    achieved = ops / (ms * 1e-3)
+    ms, _, nl = kern["single"]
+    achieved = ops / (span_ms * 1e-3)
     res = out.cpu().numpy()
     brute = [p.n * (p.n - 1) * (4 * sum(p.dims) + 2) for p in probs]
     n_win = sum(1 for p in probs if p.k <= 4 and p.n >= 2048 and p.dims[2] >= 1)
@@ -485,8 +487,10 @@ def uneven_bench(ksg, args):
                      "frac": round(achieved / PEAK_VALU, 4), "traffic": None,
                      "frac_4cycle_class": round(achieved / PEAK_VALU_4CYCLE, 4),
                      "kernel": "single-problem search kernels (brute force per shape or width, and "
-                               "the key-ordered window search; operations over the pairs each visits)",
-                     "kernel_ms_per_step": round(ms / args.steps, 3),
+                               "the key-ordered window search; operations over the pairs each visits), "
+                               "one launch per column count, run side by side",
+                     "search_span_ms_per_step": round(span_ms / args.steps, 3),
+                     "kernel_ms_sum_per_step": round(ms / args.steps, 3),
                      "launches_per_step": nl / args.steps, "ops_per_step": ops / args.steps,
                      "brute_force_ops_per_step": float(sum(brute))},
     }

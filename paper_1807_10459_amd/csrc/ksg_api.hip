@@ -230,6 +230,14 @@ extern "C" void ksg_ctx_destroy(ksg_ctx* c) {
   if (c->h_ms) (void)hipHostFree(c->h_ms);
   if (c->staging) (void)hipHostFree(c->staging);
   if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+  for (int i = 0; i < ksg_ctx::kAuxStreams; ++i) {
+    if (c->aux_streams[i]) {
+      (void)hipStreamSynchronize(c->aux_streams[i]);
+      (void)hipStreamDestroy(c->aux_streams[i]);
+    }
+    if (c->join_ev[i]) (void)hipEventDestroy(c->join_ev[i]);
+  }
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   for (auto& pr : c->timed) c->event_pool.insert(c->event_pool.end(), {pr.first, pr.second});
   for (auto& sp : c->spans) c->event_pool.insert(c->event_pool.end(), {sp.a, sp.b});
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
@@ -570,7 +578,9 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   // ungrouped work items (algorithm 2: one launch per column count, items in D order)
   struct Segment {
     int D, kp, off, count;
+    double cost;  // brute-force operations of its problems (launch scheduling)
   };
+  double plain_cost = 0.0;
   std::vector<Segment> segments;
   std::vector<WorkItem> items;
   if (algorithm == 2) {
@@ -585,13 +595,16 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     }
     for (auto& kv : by_d) {
       std::vector<WorkItem> seg = order_items(kv.second);
-      segments.push_back(Segment{kv.first, kp_of[kv.first], (int)items.size(), (int)seg.size()});
+      double c = 0.0;
+      for (const Unit& u : kv.second) c += u.cost;
+      segments.push_back(Segment{kv.first, kp_of[kv.first], (int)items.size(), (int)seg.size(), c});
       items.insert(items.end(), seg.begin(), seg.end());
     }
   } else {
     std::vector<Unit> units;
     for (int r = 0; r < np; ++r)
       if (group_of[order[r]] < 0 && win_of[order[r]] < 0) units.push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
+    for (const Unit& u : units) plain_cost += u.cost;
     items = order_items(units);
   }
   // window problems: one launch per column count, after the other ungrouped items
@@ -604,7 +617,9 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     }
     for (auto& kv : by_d) {
       std::vector<WorkItem> seg = order_items(kv.second);
-      wsegments.push_back(Segment{kv.first, 5, (int)items.size(), (int)seg.size()});
+      double c = 0.0;
+      for (const Unit& u : kv.second) c += u.cost;
+      wsegments.push_back(Segment{kv.first, 5, (int)items.size(), (int)seg.size(), c});
       items.insert(items.end(), seg.begin(), seg.end());
     }
   }
@@ -801,57 +816,104 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   float* d_e = static_cast<float*>(ebuf.ptr);
   double* d_t = static_cast<double*>(tbuf.ptr);
   unsigned long long* d_w = timing ? d_work : nullptr;
-  // In timing mode every launch is bracketed by its own pair of events (per-kernel times).
+  // In timing mode every launch is bracketed by its own pair of events (per-kernel times),
+  // recorded on the stream the launch goes to.
   hipEvent_t span_a = nullptr;
-  auto span_begin = [&]() -> int {
+  auto span_begin = [&](hipStream_t st_) -> int {
     if (!timing) return KSG_OK;
     span_a = get_event();
     if (!span_a) return fail(KSG_EDEVICE, "cannot create timing events");
-    KSG_HIP(this, hipEventRecord(span_a, stream));
+    KSG_HIP(this, hipEventRecord(span_a, st_));
     return KSG_OK;
   };
-  auto span_end = [&](int kind) -> int {
+  auto span_end = [&](int kind, hipStream_t st_) -> int {
     if (!timing) return KSG_OK;
     hipEvent_t b = get_event();
     if (!b) return fail(KSG_EDEVICE, "cannot create timing events");
-    KSG_HIP(this, hipEventRecord(b, stream));
+    KSG_HIP(this, hipEventRecord(b, st_));
     spans.push_back(Span{span_a, b, kind});
     return KSG_OK;
   };
+
+  // Single-problem launches (one per column count or shape; none of them reads another's
+  // output) are spread over the auxiliary streams, longest first onto the least-loaded
+  // stream, so that launches too small to fill the device run side by side.  Grouped chunks
+  // stay on the context's stream.
+  struct Launch {
+    int kind;  // 0 brute-force items, 1 window segment, 2 algorithm-2 segment
+    int seg;
+    double cost;
+  };
+  std::vector<Launch> launches;
+  if (algorithm == 2) {
+    for (size_t g = 0; g < segments.size(); ++g) launches.push_back(Launch{2, (int)g, segments[g].cost});
+  } else {
+    if (n_plain_items > 0) launches.push_back(Launch{0, 0, plain_cost});
+    for (size_t g = 0; g < wsegments.size(); ++g) launches.push_back(Launch{1, (int)g, wsegments[g].cost});
+  }
+  const bool fork = launches.size() + (chunks.empty() ? 0 : 1) > 1;
+  std::vector<hipStream_t> launch_stream(launches.size(), stream);
+  bool aux_used[ksg_ctx::kAuxStreams] = {false, false, false};
+  if (fork) {
+    if ((st = ensure_aux_streams())) return st;
+    std::vector<int> by_cost(launches.size());
+    for (size_t i = 0; i < launches.size(); ++i) by_cost[i] = (int)i;
+    std::stable_sort(by_cost.begin(), by_cost.end(),
+                     [&](int a, int b) { return launches[a].cost > launches[b].cost; });
+    // candidate streams: the context's (only when it runs no grouped chunk) and the auxiliaries
+    std::vector<std::pair<hipStream_t, double>> load;
+    if (chunks.empty()) load.emplace_back(stream, 0.0);
+    for (int i = 0; i < ksg_ctx::kAuxStreams; ++i) load.emplace_back(aux_streams[i], 0.0);
+    for (int li : by_cost) {
+      size_t best = 0;
+      for (size_t j = 1; j < load.size(); ++j)
+        if (load[j].second < load[best].second) best = j;
+      load[best].second += launches[li].cost;
+      launch_stream[li] = load[best].first;
+      for (int i = 0; i < ksg_ctx::kAuxStreams; ++i)
+        if (load[best].first == aux_streams[i]) aux_used[i] = true;
+    }
+    KSG_HIP(this, hipEventRecord(fork_ev, stream));
+    for (int i = 0; i < ksg_ctx::kAuxStreams; ++i)
+      if (aux_used[i]) KSG_HIP(this, hipStreamWaitEvent(aux_streams[i], fork_ev, 0));
+  }
+  for (size_t li = 0; li < launches.size(); ++li) {
+    const Launch& L = launches[li];
+    const hipStream_t ls = launch_stream[li];
+    if ((st = span_begin(ls))) return st;
+    if (L.kind == 2) {
+      const Segment& g = segments[L.seg];
+      KSG_HIP(this, launch_ksg_alg2((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
+                                    (double*)partials.ptr, g.D, g.kp, ls));
+    } else if (L.kind == 1) {
+      const Segment& g = wsegments[L.seg];
+      KSG_HIP(this, launch_ksg_window((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
+                                      (double*)partials.ptr, g.D, d_w, ls));
+    } else {
+      KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items, n_plain_items, (const double*)htab.ptr,
+                                      (double*)partials.ptr, common_shape, kp, ls));
+    }
+    if ((st = span_end(3, ls))) return st;
+  }
   for (const Chunk& c : chunks) {
     const int m = c.cls[0], G = c.cls[1], kp_c = c.cls[2];
-    if ((st = span_begin())) return st;
+    if ((st = span_begin(stream))) return st;
     KSG_HIP(this, launch_ksg_group_radius(pool_base, d_gdesc, d_items + c.item_off, (int)c.items.size(), d_e,
                                           m, G, kp_c, d_w, stream));
-    if ((st = span_end(0)) || (st = span_begin())) return st;
+    if ((st = span_end(0, stream)) || (st = span_begin(stream))) return st;
     KSG_HIP(this, launch_ksg_yzcount(pool_base, d_ydesc, d_items + c.yitem_off, (int)c.n_yitems, d_e, d_t,
                                      (const double*)htab.ptr, m, d_w, stream));
-    if ((st = span_end(1)) || (st = span_begin())) return st;
+    if ((st = span_end(1, stream)) || (st = span_begin(stream))) return st;
     KSG_HIP(this, launch_ksg_group_xcount(pool_base, d_gdesc, d_items + c.item_off, (int)c.items.size(), d_e,
                                           d_t, (const double*)htab.ptr, (double*)partials.ptr, m, G, d_w,
                                           stream));
-    if ((st = span_end(2))) return st;
+    if ((st = span_end(2, stream))) return st;
   }
-  if (algorithm == 2) {
-    for (const Segment& g : segments) {
-      if ((st = span_begin())) return st;
-      KSG_HIP(this, launch_ksg_alg2((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
-                                    (double*)partials.ptr, g.D, g.kp, stream));
-      if ((st = span_end(3))) return st;
-    }
-  } else {
-    if (n_plain_items > 0) {
-      const int shape = common_shape;
-      if ((st = span_begin())) return st;
-      KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items, n_plain_items, (const double*)htab.ptr,
-                                      (double*)partials.ptr, shape, kp, stream));
-      if ((st = span_end(3))) return st;
-    }
-    for (const Segment& g : wsegments) {
-      if ((st = span_begin())) return st;
-      KSG_HIP(this, launch_ksg_window((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
-                                      (double*)partials.ptr, g.D, d_w, stream));
-      if ((st = span_end(3))) return st;
+  if (fork) {
+    for (int i = 0; i < ksg_ctx::kAuxStreams; ++i) {
+      if (!aux_used[i]) continue;
+      KSG_HIP(this, hipEventRecord(join_ev[i], aux_streams[i]));
+      KSG_HIP(this, hipStreamWaitEvent(stream, join_ev[i], 0));
     }
   }
   if (timing) {
@@ -1011,6 +1073,16 @@ extern "C" int ksg_embed(ksg_ctx* c, const float* data, int32_t n_vars, int64_t 
 }
 
 // ============================================================== timing
+
+int ksg_ctx::ensure_aux_streams() {
+  if (fork_ev) return KSG_OK;
+  for (int i = 0; i < kAuxStreams; ++i) {
+    KSG_HIP(this, hipStreamCreateWithFlags(&aux_streams[i], hipStreamNonBlocking));
+    KSG_HIP(this, hipEventCreateWithFlags(&join_ev[i], hipEventDisableTiming));
+  }
+  KSG_HIP(this, hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+  return KSG_OK;
+}
 
 hipEvent_t ksg_ctx::get_event() {
   if (!event_pool.empty()) {

@@ -158,6 +158,25 @@ __device__ __forceinline__ void window_count_dx1(const cfptr (&col)[D], const fl
   }
 }
 
+// Count pass for dx == 2 (so dy >= 2 in the canonical split, and dz >= 1 for a window
+// problem): one compile-time loop per dy in [DY, D - 3].
+template <int D, int DY, class OpenR, class OpenL>
+__device__ __forceinline__ void window_count_dx2(const cfptr (&col)[D], const float (&q)[D], int dy, float eps,
+                                                 int s_lo, int s_hi, int steps, OpenR open_r, OpenL open_l,
+                                                 unsigned (&acc)[3], unsigned& n_steps) {
+  if constexpr (DY < D - 3) {
+    if (dy == DY) {
+      window_scan(s_lo, s_hi, steps, [&](int s) { window_count_step<2, DY, D - 2 - DY>(col, q, s, eps, acc); },
+                  open_r, open_l, n_steps);
+      return;
+    }
+    window_count_dx2<D, DY + 1>(col, q, dy, eps, s_lo, s_hi, steps, open_r, open_l, acc, n_steps);
+  } else {
+    window_scan(s_lo, s_hi, steps, [&](int s) { window_count_step<2, D - 3, 1>(col, q, s, eps, acc); }, open_r,
+                open_l, n_steps);
+  }
+}
+
 template <int D, int KP>
 __global__ __launch_bounds__(kTileQ) void ksg_window_kernel(const ProbDesc* __restrict__ descs,
                                                             const WorkItem* __restrict__ items,
@@ -288,9 +307,18 @@ __global__ __launch_bounds__(kTileQ) void ksg_window_kernel(const ProbDesc* __re
   unsigned acc[3] = {0u, 0u, 0u};
   auto open_r2 = [&](int s) { return __builtin_amdgcn_ballot_w64(fabsf(kcol[4 * s] - qkey) < eps) != 0; };
   auto open_l2 = [&](int s) { return __builtin_amdgcn_ballot_w64(fabsf(kcol[4 * s + 3] - qkey) < eps) != 0; };
-  if (dx == 1)
+  bool counted = false;
+  if (dx == 1) {
     window_count_dx1<D, 1>(col, q, dy, eps, s_lo, s_hi, steps, open_r2, open_l2, acc, n2);
-  else
+    counted = true;
+  }
+  if constexpr (D >= 5) {
+    if (dx == 2) {
+      window_count_dx2<D, 2>(col, q, dy, eps, s_lo, s_hi, steps, open_r2, open_l2, acc, n2);
+      counted = true;
+    }
+  }
+  if (!counted)
     window_scan(s_lo, s_hi, steps, [&](int s) { window_count_step_split<D>(col, q, s, eps, dx, dy, acc); },
                 open_r2, open_l2, n2);
   if (work && (threadIdx.x & 63) == 0)

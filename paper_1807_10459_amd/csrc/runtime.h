@@ -67,6 +67,15 @@ struct ksg_ctx {
   ksg::MaxStatOut* d_ms = nullptr;
   ksg::MaxStatOut* h_ms = nullptr;  // pinned
 
+  // Auxiliary streams (default priority) on which the single-problem search launches of one
+  // batch run side by side (one launch per column count or shape): forked from and joined
+  // back to `stream` through events, created on first use.
+  static constexpr int kAuxStreams = 3;
+  hipStream_t aux_streams[kAuxStreams] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kAuxStreams] = {};
+  int ensure_aux_streams();
+
   void* staging = nullptr;  // pinned upload block
   size_t staging_cap = 0;
   hipEvent_t staging_done = nullptr;
