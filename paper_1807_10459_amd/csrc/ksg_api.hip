@@ -877,45 +877,57 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     for (int i = 0; i < ksg_ctx::kAuxStreams; ++i)
       if (aux_used[i]) KSG_HIP(this, hipStreamWaitEvent(aux_streams[i], fork_ev, 0));
   }
-  for (size_t li = 0; li < launches.size(); ++li) {
-    const Launch& L = launches[li];
-    const hipStream_t ls = launch_stream[li];
-    if ((st = span_begin(ls))) return st;
-    if (L.kind == 2) {
-      const Segment& g = segments[L.seg];
-      KSG_HIP(this, launch_ksg_alg2((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
-                                    (double*)partials.ptr, g.D, g.kp, ls));
-    } else if (L.kind == 1) {
-      const Segment& g = wsegments[L.seg];
-      KSG_HIP(this, launch_ksg_window((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
-                                      (double*)partials.ptr, g.D, d_w, ls));
-    } else {
-      KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items, n_plain_items, (const double*)htab.ptr,
-                                      (double*)partials.ptr, common_shape, kp, ls));
+  // Every launch is enqueued by this lambda; whatever it returns, the auxiliary streams are
+  // joined back before run_batch returns, so that later work on the context's stream (and
+  // a buffer reallocation, which synchronises that stream) orders after them.
+  auto enqueue_search = [&]() -> int {
+    for (size_t li = 0; li < launches.size(); ++li) {
+      const Launch& L = launches[li];
+      const hipStream_t ls = launch_stream[li];
+      if ((st = span_begin(ls))) return st;
+      if (L.kind == 2) {
+        const Segment& g = segments[L.seg];
+        KSG_HIP(this, launch_ksg_alg2((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
+                                      (double*)partials.ptr, g.D, g.kp, ls));
+      } else if (L.kind == 1) {
+        const Segment& g = wsegments[L.seg];
+        KSG_HIP(this, launch_ksg_window((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
+                                        (double*)partials.ptr, g.D, d_w, ls));
+      } else {
+        KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items, n_plain_items, (const double*)htab.ptr,
+                                        (double*)partials.ptr, common_shape, kp, ls));
+      }
+      if ((st = span_end(3, ls))) return st;
     }
-    if ((st = span_end(3, ls))) return st;
-  }
-  for (const Chunk& c : chunks) {
-    const int m = c.cls[0], G = c.cls[1], kp_c = c.cls[2];
-    if ((st = span_begin(stream))) return st;
-    KSG_HIP(this, launch_ksg_group_radius(pool_base, d_gdesc, d_items + c.item_off, (int)c.items.size(), d_e,
-                                          m, G, kp_c, d_w, stream));
-    if ((st = span_end(0, stream)) || (st = span_begin(stream))) return st;
-    KSG_HIP(this, launch_ksg_yzcount(pool_base, d_ydesc, d_items + c.yitem_off, (int)c.n_yitems, d_e, d_t,
-                                     (const double*)htab.ptr, m, d_w, stream));
-    if ((st = span_end(1, stream)) || (st = span_begin(stream))) return st;
-    KSG_HIP(this, launch_ksg_group_xcount(pool_base, d_gdesc, d_items + c.item_off, (int)c.items.size(), d_e,
-                                          d_t, (const double*)htab.ptr, (double*)partials.ptr, m, G, d_w,
-                                          stream));
-    if ((st = span_end(2, stream))) return st;
-  }
+    for (const Chunk& c : chunks) {
+      const int m = c.cls[0], G = c.cls[1], kp_c = c.cls[2];
+      if ((st = span_begin(stream))) return st;
+      KSG_HIP(this, launch_ksg_group_radius(pool_base, d_gdesc, d_items + c.item_off, (int)c.items.size(), d_e,
+                                            m, G, kp_c, d_w, stream));
+      if ((st = span_end(0, stream)) || (st = span_begin(stream))) return st;
+      KSG_HIP(this, launch_ksg_yzcount(pool_base, d_ydesc, d_items + c.yitem_off, (int)c.n_yitems, d_e, d_t,
+                                       (const double*)htab.ptr, m, d_w, stream));
+      if ((st = span_end(1, stream)) || (st = span_begin(stream))) return st;
+      KSG_HIP(this, launch_ksg_group_xcount(pool_base, d_gdesc, d_items + c.item_off, (int)c.items.size(), d_e,
+                                            d_t, (const double*)htab.ptr, (double*)partials.ptr, m, G, d_w,
+                                            stream));
+      if ((st = span_end(2, stream))) return st;
+    }
+    return KSG_OK;
+  };
+  const int st_search = enqueue_search();
   if (fork) {
     for (int i = 0; i < ksg_ctx::kAuxStreams; ++i) {
       if (!aux_used[i]) continue;
-      KSG_HIP(this, hipEventRecord(join_ev[i], aux_streams[i]));
-      KSG_HIP(this, hipStreamWaitEvent(stream, join_ev[i], 0));
+      hipError_t e = hipEventRecord(join_ev[i], aux_streams[i]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(stream, join_ev[i], 0);
+      if (e != hipSuccess) {
+        (void)hipStreamSynchronize(aux_streams[i]);
+        if (!st_search) return hip_fail(e, "joining an auxiliary stream");
+      }
     }
   }
+  if (st_search) return st_search;
   if (timing) {
     KSG_HIP(this, hipEventRecord(t1, stream));
     timed.emplace_back(t0, t1);
@@ -1076,11 +1088,24 @@ extern "C" int ksg_embed(ksg_ctx* c, const float* data, int32_t n_vars, int64_t 
 
 int ksg_ctx::ensure_aux_streams() {
   if (fork_ev) return KSG_OK;
-  for (int i = 0; i < kAuxStreams; ++i) {
-    KSG_HIP(this, hipStreamCreateWithFlags(&aux_streams[i], hipStreamNonBlocking));
-    KSG_HIP(this, hipEventCreateWithFlags(&join_ev[i], hipEventDisableTiming));
+  // all or nothing: fork_ev is set last, and a failure releases what was created
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < kAuxStreams && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&aux_streams[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join_ev[i], hipEventDisableTiming);
   }
-  KSG_HIP(this, hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+  hipEvent_t f = nullptr;
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&f, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    for (int i = 0; i < kAuxStreams; ++i) {
+      if (aux_streams[i]) (void)hipStreamDestroy(aux_streams[i]);
+      if (join_ev[i]) (void)hipEventDestroy(join_ev[i]);
+      aux_streams[i] = nullptr;
+      join_ev[i] = nullptr;
+    }
+    return hip_fail(e, "creating the auxiliary streams");
+  }
+  fork_ev = f;
   return KSG_OK;
 }
 
