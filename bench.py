@@ -579,7 +579,9 @@ def main():
                  "v_add_u32", "v_cmp_lt_f32 -> SGPR pair", "v_and_b32", "v_sub_f32 SGPR operand",
                  "v_min3_f32", "v_sub_u32", "v_lshrrev_b32", "v_add3_u32", "v_mov_b32 from SGPR"]
         rates = {f"{i} {n}": round(ctx.valu_probe(i) / 1e12, 2) for i, n in enumerate(names)}
-        print(json.dumps({"valu_probe_T_lane_ops_per_s": rates}))
+        lds = ctx.lds_probe()
+        print(json.dumps({"valu_probe_T_lane_ops_per_s": rates, "lds_read_TB_per_s": round(lds / 1e12, 2),
+                          "lds_read_bytes_per_clk_per_cu": round(lds / (ksg.device_props(0)["cus"] * 2.4e9), 1)}))
         return
 
     if args.workload == "c4":

@@ -156,6 +156,12 @@ int ksg_autotune(ksg_ctx* ctx, int64_t n, const char* cache_path, int32_t* tuned
  * Errors: KSG_EINVAL, KSG_EDEVICE. */
 int ksg_valu_probe(ksg_ctx* ctx, int32_t kind, int32_t iters, double* lane_ops_per_s);
 
+/* LDS read bandwidth of the context's device in bytes per second: 8 work-groups of 256 lanes
+ * per CU, each lane reading 8 independent 16-byte values per iteration from a 64 KB LDS
+ * array without bank conflicts, iters iterations.  Synchronises.  Output is a host pointer.
+ * Errors: KSG_EINVAL, KSG_EDEVICE. */
+int ksg_lds_probe(ksg_ctx* ctx, int32_t iters, double* bytes_per_s);
+
 /* With KSG_OPT_TIMING on: device time of the search kernels (radius, counts and per-tile
  * digamma sums, finalisation excluded) summed over all search phases since the last call, in
  * milliseconds, with their count and algorithmic operation count.  Problems searched alone

@@ -88,6 +88,7 @@ def _load():
         "ksg_ctx_set_option": ([vp, i32, i64], i32),
         "ksg_autotune": ([vp, i64, C.c_char_p, vp], i32),
         "ksg_valu_probe": ([vp, i32, i32, C.POINTER(d)], i32),
+        "ksg_lds_probe": ([vp, i32, C.POINTER(d)], i32),
         "ksg_last_work": ([vp, vp], i32),
         "ksg_last_kernels": ([vp, vp, vp, vp], i32),
         "ksg_take_timing": ([vp, C.POINTER(d), C.POINTER(i64), C.POINTER(d)], i32),
@@ -282,6 +283,12 @@ class Context:
         """Lane operations per second of one VALU instruction class (see ksg_valu_probe)."""
         r = C.c_double()
         self._check(lib.ksg_valu_probe(self._h, int(kind), int(iters), C.byref(r)), "ksg_valu_probe")
+        return r.value
+
+    def lds_probe(self, iters: int = 4096) -> float:
+        """LDS read bytes per second of the device (see ksg_lds_probe)."""
+        r = C.c_double()
+        self._check(lib.ksg_lds_probe(self._h, int(iters), C.byref(r)), "ksg_lds_probe")
         return r.value
 
     def take_timing(self):

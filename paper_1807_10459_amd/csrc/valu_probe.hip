@@ -68,9 +68,59 @@ __global__ __launch_bounds__(256) void valu_probe_kernel(int iters, float seed, 
   if (acc == 12345.678f) out[threadIdx.x] = acc;  // keeps the chains live
 }
 
+// LDS read bandwidth: each lane reads 8 independent float4 values per iteration from a 64 KB
+// LDS array (consecutive lanes at consecutive 16-byte addresses, so no bank conflicts), the
+// address alternating between its two halves so that the reads cannot be hoisted out of the
+// loop; all 8 reads are issued before empty asm statements take the loaded registers, so the
+// reads stay 128-bit, overlap, and no arithmetic follows them.
+__global__ __launch_bounds__(256) void lds_probe_kernel(int iters, float seed, float* __restrict__ out) {
+  constexpr int kHalf = 2048;  // float4 per half
+  __shared__ float4 s[2 * kHalf];
+  for (int i = (int)threadIdx.x; i < 2 * kHalf; i += 256)
+    s[i] = make_float4(seed + (float)i, seed - (float)i, seed * (float)i, (float)i);
+  __syncthreads();
+  const int lane = (int)threadIdx.x;
+  for (int it = 0; it < iters; ++it) {
+    const float4* h = s + (it & 1) * kHalf + lane;
+    float4 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = h[i * 256];  // all 8 reads in flight before the first use
+#pragma unroll
+    for (int i = 0; i < 8; ++i) asm volatile("" : : "v"(v[i].x), "v"(v[i].y), "v"(v[i].z), "v"(v[i].w));
+  }
+  if (seed == 12345.678f) out[threadIdx.x] = s[lane].x;
+}
+
 }  // namespace ksg
 
 using namespace ksg;
+
+extern "C" int ksg_lds_probe(ksg_ctx* c, int32_t iters, double* bytes_per_s) {
+  if (!c) return KSG_EINVAL;
+  if (!bytes_per_s || iters < 1) return c->fail(KSG_EINVAL, "ksg_lds_probe: bad argument");
+  if (hipSetDevice(c->device) != hipSuccess) return c->fail(KSG_EDEVICE, "hipSetDevice");
+  const int blocks = c->cus * 8;
+  int st = c->reserve(c->tmp, 256 * sizeof(float), "probe output");
+  if (st) return st;
+  float seed = 1.25f;
+  float* out = (float*)c->tmp.ptr;
+  void* args[] = {&iters, &seed, &out};
+  hipEvent_t e0 = c->get_event(), e1 = c->get_event();
+  if (!e0 || !e1) return c->fail(KSG_EDEVICE, "events");
+  const void* fn = (const void*)&lds_probe_kernel;
+  hipError_t e = hipLaunchKernel(fn, dim3(blocks), dim3(256), args, 0, c->stream);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+  if (e == hipSuccess) e = hipLaunchKernel(fn, dim3(blocks), dim3(256), args, 0, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  c->event_pool.push_back(e0);
+  c->event_pool.push_back(e1);
+  if (e != hipSuccess) return c->hip_fail(e, "lds probe");
+  *bytes_per_s = (double)iters * 8.0 * 16.0 * 256.0 * (double)blocks / (ms * 1e-3);
+  return KSG_OK;
+}
 
 extern "C" int ksg_valu_probe(ksg_ctx* c, int32_t kind, int32_t iters, double* lane_ops_per_s) {
   if (!c) return KSG_EINVAL;

@@ -394,6 +394,17 @@ def test_valu_probe_classes(lib, ctx):
         ctx.valu_probe(18)
 
 
+def test_lds_probe(lib, ctx):
+    """The LDS read bandwidth probe runs and reports between 32 and 512 bytes per clock per CU
+    at the 2.4 GHz engine clock (the part's LDS serves 128 bytes per clock or more)."""
+    r = ctx.lds_probe(iters=512)
+    per_clk = r / (lib.device_props(0)["cus"] * 2.4e9)
+    print("LDS bytes/clk/CU", per_clk)
+    assert 32 < per_clk < 512, per_clk
+    with pytest.raises(lib.KsgError):
+        ctx.lds_probe(0)
+
+
 def test_device_props(lib):
     """The runtime's figures for the device the roofline is priced on."""
     import torch
