@@ -526,17 +526,21 @@ def _kernel_source_hash():
                                    for f in TRAFFIC_SOURCES)).hexdigest()
 
 
-def _traffic_record(kernel):
-    """HBM bytes per launch of a kernel from the committed counter record, or None when the
-    kernel sources changed since the counters were taken."""
+def _counter_record(field, kernel):
+    """A per-launch figure of a kernel from the committed counter record (HBM bytes, VALU
+    wave-instructions), or None when the kernel sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "ksg_group_kernels_traffic.json")
     try:
         rec = json.load(open(path))
         if _kernel_source_hash() == rec["kernel_source_sha256"]:
-            return rec["traffic_bytes_per_launch"].get(kernel)
+            return rec[field].get(kernel)
     except (OSError, KeyError, ValueError, AttributeError):
         pass
     return None
+
+
+def _traffic_record(kernel):
+    return _counter_record("traffic_bytes_per_launch", kernel)
 
 
 def main():
@@ -701,6 +705,11 @@ def main():
         "frac": round(achieved / PEAK_VALU, 4),
         "frac_4cycle_class": round(achieved / PEAK_VALU_4CYCLE, 4),
         "traffic": _traffic_record(dom),
+        # executed VALU lane-instructions (SQ_INSTS_VALU x 64, committed counter record) over
+        # 39.3 T lane-instructions/s (one instruction per 4 cycles per SIMD) x this run's time
+        "valu_issue_frac_4cycle": (None if _counter_record("valu_wave_instructions_per_launch", dom) is None
+                                   else round(_counter_record("valu_wave_instructions_per_launch", dom) * 64
+                                              / (PEAK_VALU_4CYCLE * d_ms / d_n * 1e-3), 3)),
         "kernel": KERNEL_NAMES["alg2"] if args.algorithm == 2 else
                   KERNEL_NAMES["window" if dom == "single" and not args.no_windows else dom],
         "kernel_ms_per_launch": round(d_ms / d_n, 3),
