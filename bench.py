@@ -334,6 +334,7 @@ def omnibus_bench(ksg, args):
     data = torch.from_numpy(net.data).cuda()
     ctx = ksg.Context(0)
     ctx.set_option(ctx.OPT_WINDOWS, 0 if args.no_windows else 1)
+    ctx.set_option(ctx.OPT_ALGORITHM, args.algorithm)
     cand, y = ctx.embed(data, target=0, max_lag=MAX_LAG)
     N = y.shape[0]
     idx = [v * MAX_LAG + lag - 1 for (v, lag) in OMNIBUS_PARENTS]
@@ -364,7 +365,8 @@ def omnibus_bench(ksg, args):
     achieved = ops / (ms * 1e-3)
     res = out.cpu().numpy()
     line = {
-        "metric": "CMI estimates/sec incl. surrogates (omnibus test, N=29950, k=4)",
+        "metric": "CMI estimates/sec incl. surrogates (omnibus test, N=29950, k=4)"
+                  + (", KSG algorithm 2" if args.algorithm == 2 else ""),
         "value": round((P + 1) * args.steps / wall, 1),
         "unit": "CMI/s",
         "n_gpus": 1,
@@ -384,7 +386,7 @@ def omnibus_bench(ksg, args):
                      "peak": round(PEAK_VALU / 1e12, 3), "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_VALU, 4), "traffic": None,
                      "frac_4cycle_class": round(achieved / PEAK_VALU_4CYCLE, 4),
-                     "kernel": KERNEL_NAMES["single"] if args.no_windows else KERNEL_NAMES["window"],
+                     "kernel": KERNEL_NAMES["alg2" if args.algorithm == 2 else "single"] if args.no_windows else KERNEL_NAMES["window"],
                      "kernel_ms_per_launch": round(ms / nl, 3),
                      "launches": nl, "ops_per_launch": ops / nl},
         "omnibus_cmi": float(res[0]),
@@ -392,9 +394,10 @@ def omnibus_bench(ksg, args):
     }
     if not args.no_cpu_baseline:
         from oracle.ksg import ksg_cmi
+        from oracle.ksg2 import ksg2_cmi
         xs_np, y_np, zs_np = xs.cpu().numpy().T, y.cpu().numpy(), zs.cpu().numpy().T
         t1 = time.perf_counter()
-        ref = ksg_cmi(xs_np, y_np, zs_np, K)
+        ref = (ksg2_cmi if args.algorithm == 2 else ksg_cmi)(xs_np, y_np, zs_np, K)
         dt = time.perf_counter() - t1
         line["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "CMI/s", "cores": 1, "kind": "oracle",
                                 "cpu_model": _cpu_model(),

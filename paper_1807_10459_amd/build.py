@@ -22,6 +22,7 @@ SOURCES = [
     "ksg_yzcount.hip",
     "ksg_alg2.hip",
     "ksg_window.hip",
+    "ksg_window_alg2.hip",
     "ksg_misc.hip",
     "ksg_api.hip",
     "greedy.hip",

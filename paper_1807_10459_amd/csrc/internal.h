@@ -13,7 +13,7 @@ constexpr int kMaxK = 16;
 constexpr int kWindowMinN = 2048;  // smallest N searched with key-ordered windows (single problems)
 
 // One CMI problem as the search kernel sees it.  Columns are ordered X..., Y..., Z...,
-// each padded with +inf rows up to n_pad.  128 + 64 bytes, 16-byte aligned.
+// each padded with +inf rows up to n_pad.  128 + 96 bytes, 16-byte aligned.
 struct alignas(16) ProbDesc {
   const float* col[kMaxDims];
   int32_t n;          // points
@@ -30,7 +30,9 @@ struct alignas(16) ProbDesc {
   int32_t alg;        // KSG algorithm: 1 (joint radius, strict counts) or 2 (rectangles)
   int32_t key_col;    // key-ordered window search: the column (a Z column) the rows are sorted by
   int32_t pad_;
+  const int32_t* key_order;  // window search: source row of each key-ordered row (n_pad entries)
 };
+static_assert(sizeof(ProbDesc) % 16 == 0, "ProbDesc is copied as an array of 16-byte aligned records");
 
 // G problems that share Y (1-D), Z (m columns), N and k and differ in a 1-D X column.
 // All offsets are in floats from one pool.  x_off / y_off / z_off locate the packed source
@@ -128,10 +130,10 @@ hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, in
                              const double* d_htab, double* d_partials, int shape, int kp,
                              hipStream_t stream);
 // Key order of one column (sigma[rank] = row) and the key-ordered window search over the work
-// items of problems that all have D columns (k <= 4).
+// items of problems that all have D columns (k <= 4), KSG algorithm alg (1 or 2).
 hipError_t launch_window_rank(const float* key, int n, int n_pad, int32_t* sigma, hipStream_t stream);
 hipError_t launch_ksg_window(const ProbDesc* d_desc, const WorkItem* d_items, int n_items, const double* d_htab,
-                             double* d_partials, int D, unsigned long long* d_work, hipStream_t stream);
+                             double* d_partials, int D, int alg, unsigned long long* d_work, hipStream_t stream);
 // KSG algorithm 2 over the work items of problems that all have D columns.
 hipError_t launch_ksg_alg2(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                            const double* d_htab, double* d_partials, int D, int kp, hipStream_t stream);

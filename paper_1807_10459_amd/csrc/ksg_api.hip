@@ -392,7 +392,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   // that share an unpermuted Z column are searched in the order of that column ----
   std::vector<int> win_of(np, -1), win_key(np, -1);  // window set, key column (original index)
   std::vector<std::pair<const float*, int64_t>> wsets;  // (key column, N)
-  if (algorithm == 1 && use_windows) {
+  if (use_windows) {
     std::map<std::pair<const float*, int64_t>, int> by_key;
     for (int i = 0; i < np; ++i) {
       const Problem& p = probs[i];
@@ -557,6 +557,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     d.swap_xy = swap ? 1 : 0;
     d.alg = algorithm;
     d.key_col = win_key[i];  // a Z column: its index is the same in the canonical order
+    d.key_order = win_of[i] >= 0 ? reinterpret_cast<const int32_t*>(pool_base + wsigma_off[win_of[i]]) : nullptr;
     if (group_of[i] >= 0) {
       const int gi = group_of[i];
       const int g = (int)(std::find(groups[gi].begin(), groups[gi].end(), i) - groups[gi].begin());
@@ -588,6 +589,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     std::map<int, int> kp_of;
     for (int r = 0; r < np; ++r) {
       const Problem& p = probs[order[r]];
+      if (win_of[order[r]] >= 0) continue;  // searched in key order below
       const int D = p.dx + p.dy + p.dz;
       by_d[D].push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
       const int need = p.k + 1 <= 5 ? 5 : (p.k + 1 <= 9 ? 9 : 17);
@@ -623,8 +625,8 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       items.insert(items.end(), seg.begin(), seg.end());
     }
   }
-  const int n_plain_items = algorithm == 2 ? (int)items.size()
-                                           : (wsegments.empty() ? (int)items.size() : wsegments[0].off);
+  // items before the window segments (brute-force items, or the algorithm-2 segments)
+  const int n_plain_items = wsegments.empty() ? (int)items.size() : wsegments[0].off;
 
   // ---- groups: descriptors, launch chunks, Y/Z count descriptors, work items ----
   // Groups of one (m, G, KP) class run as chunks of consecutive groups, each chunk three
@@ -847,10 +849,10 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   std::vector<Launch> launches;
   if (algorithm == 2) {
     for (size_t g = 0; g < segments.size(); ++g) launches.push_back(Launch{2, (int)g, segments[g].cost});
-  } else {
-    if (n_plain_items > 0) launches.push_back(Launch{0, 0, plain_cost});
-    for (size_t g = 0; g < wsegments.size(); ++g) launches.push_back(Launch{1, (int)g, wsegments[g].cost});
+  } else if (n_plain_items > 0) {
+    launches.push_back(Launch{0, 0, plain_cost});
   }
+  for (size_t g = 0; g < wsegments.size(); ++g) launches.push_back(Launch{1, (int)g, wsegments[g].cost});
   const bool fork = launches.size() + (chunks.empty() ? 0 : 1) > 1;
   std::vector<hipStream_t> launch_stream(launches.size(), stream);
   bool aux_used[ksg_ctx::kAuxStreams] = {false, false, false};
@@ -892,7 +894,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       } else if (L.kind == 1) {
         const Segment& g = wsegments[L.seg];
         KSG_HIP(this, launch_ksg_window((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
-                                        (double*)partials.ptr, g.D, d_w, ls));
+                                        (double*)partials.ptr, g.D, algorithm, d_w, ls));
       } else {
         KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items, n_plain_items, (const double*)htab.ptr,
                                         (double*)partials.ptr, common_shape, kp, ls));

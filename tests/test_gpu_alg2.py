@@ -142,3 +142,58 @@ def test_autotune_keeps_algorithm(lib, ctx):
     ctx.autotune(1024)
     p = workloads.random_problem(91, 800, 1, 1, 2, 4)
     _check_full(lib, ctx, p.x, p.y, p.z, 4, "after autotune")
+
+
+def _alg2_window_case(case):
+    """Problems that take the key-ordered window search under algorithm 2 (k <= 4, N >= 2048,
+    a Z column, no per-point outputs)."""
+    g = workloads.rng(1700 + case)
+    if case == 0:  # compile-time (1, 1) split, continuous data
+        p = workloads.random_problem(1710, 2500, 1, 1, 2, 4)
+    elif case == 1:  # integer grid 0..20: many ties at the k-th distance
+        pts = g.integers(0, 21, size=(2300, 3)).astype(np.float32)
+        p = workloads.CmiProblemData(pts[:, :1].copy(), pts[:, 1:2].copy(), pts[:, 2:].copy(), 4)
+    elif case == 2:  # run-time split (1, 2, 3) after the X/Y exchange, k = 3
+        p = workloads.random_problem(1712, 2600, 2, 1, 3, 3)
+    elif case == 3:  # values in {0, 1}: every point has duplicates, the k-th distance is 0
+        pts = g.integers(0, 2, size=(2200, 4)).astype(np.float32)
+        p = workloads.CmiProblemData(pts[:, :1].copy(), pts[:, 1:2].copy(), pts[:, 2:].copy(), 4)
+    elif case == 4:  # constant key column: every row in every window
+        p = workloads.random_problem(1714, 2048, 1, 1, 2, 2)
+        p.z[:, 0] = 0.5
+    else:  # (2, 2, 4) in [1, 2), k = 1
+        p = workloads.random_problem(1715, 2100, 2, 2, 4, 1, kind="unit12")
+    return p
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_window_search_matches_oracle(lib, ctx, case):
+    """Algorithm 2 on the key-ordered window search: the estimates equal the algorithm-2
+    oracle's, and the brute-force kernel's up to the FP64 summation order; the window path
+    runs (its operation count stays below the brute force's except for a constant key)."""
+    p = _alg2_window_case(case)
+    n = p.n
+    perms = workloads.permutations(n, 2, seed=1720 + case)
+    xd, yd, zd = soa(p.x), soa(p.y), soa(p.z)
+    dp = dev(perms)
+    probs = [lib.Problem(xd, yd, zd, p.k)] + [lib.Problem(xd, yd, zd, p.k, perm_x=dp[q]) for q in range(2)]
+    got, ops = {}, {}
+    ctx.set_option(ctx.OPT_TIMING, 1)
+    try:
+        for w in (1, 0):
+            ctx.set_option(ctx.OPT_WINDOWS, w)
+            ctx.take_timing()
+            got[w] = ctx.cmi_batch(probs).cpu().numpy()
+            ops[w] = ctx.take_timing()[2]
+    finally:
+        ctx.set_option(ctx.OPT_WINDOWS, 1)
+        ctx.set_option(ctx.OPT_TIMING, 0)
+    h = float(np.sum(1.0 / np.arange(1, n + 1)))
+    bound = 2 * 9 * 2.0 ** -53 * 4 * (h + 2.0)  # per-point terms bounded by 3 H_n + 2
+    assert np.max(np.abs(got[1] - got[0])) <= bound, (case, got[1] - got[0])
+    if case != 4:
+        assert 0 < ops[1] < ops[0], (case, ops)
+    for q in range(3):
+        xs = p.x if q == 0 else p.x[perms[q - 1]]
+        ref = ksg2_cmi(xs, p.y, p.z, p.k)
+        assert abs(got[1][q] - ref) <= tol(ref), (case, q, got[1][q], ref)
