@@ -386,7 +386,8 @@ def omnibus_bench(ksg, args):
                      "peak": round(PEAK_VALU / 1e12, 3), "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_VALU, 4), "traffic": None,
                      "frac_4cycle_class": round(achieved / PEAK_VALU_4CYCLE, 4),
-                     "kernel": KERNEL_NAMES["alg2" if args.algorithm == 2 else "single"] if args.no_windows else KERNEL_NAMES["window"],
+                     "kernel": KERNEL_NAMES[("alg2" if args.algorithm == 2 else "single") if args.no_windows
+                                            else ("window_alg2" if args.algorithm == 2 else "window")],
                      "kernel_ms_per_launch": round(ms / nl, 3),
                      "launches": nl, "ops_per_launch": ops / nl},
         "omnibus_cmi": float(res[0]),
@@ -417,7 +418,9 @@ KERNEL_NAMES = {"radius": "ksg_group_radius_kernel (k-NN radius of each problem 
                 "window": "ksg_window_kernel (rows in key order, radius and counts within each tile's "
                           "key window; operations counted over the pairs visited)",
                 "alg2": "ksg_alg2_kernel (KSG algorithm 2: indexed top-k, neighbour rectangles, "
-                        "rectangle counts and partial sums)"}
+                        "rectangle counts and partial sums)",
+                "window_alg2": "ksg_window_kernel<D, 5, 2> (KSG algorithm 2 in key order: k-th neighbour "
+                               "distance, rectangle sides, <= counts; operations counted over the pairs visited)"}
 
 
 def _cpu_model():
@@ -713,8 +716,8 @@ def main():
         "valu_issue_frac_4cycle": (None if _counter_record("valu_wave_instructions_per_launch", dom) is None
                                    else round(_counter_record("valu_wave_instructions_per_launch", dom) * 64
                                               / (PEAK_VALU_4CYCLE * d_ms / d_n * 1e-3), 3)),
-        "kernel": KERNEL_NAMES["alg2"] if args.algorithm == 2 else
-                  KERNEL_NAMES["window" if dom == "single" and not args.no_windows else dom],
+        "kernel": KERNEL_NAMES[("alg2" if args.no_windows else "window_alg2") if args.algorithm == 2 else
+                               ("window" if dom == "single" and not args.no_windows else dom)],
         "kernel_ms_per_launch": round(d_ms / d_n, 3),
         "launches": d_n,
         "ops_per_launch": d_ops / d_n,

@@ -132,8 +132,10 @@ typedef enum ksg_option {
   KSG_OPT_WINDOWS = 6       /* 1 (default): single problems (not grouped) with k <= 4, N >= 2048,
                              * no per-point outputs and an unpermuted Z column are searched with
                              * their rows in the order of that column, each tile scanning only the
-                             * rows its radii and counts can reach (same results up to the order
-                             * of the FP64 sum); 0: brute force over all rows */
+                             * rows its radii, rectangle sides and counts can reach (same results
+                             * up to the order of the FP64 sum; either KSG algorithm; under
+                             * algorithm 2 neighbours tied at the k-th distance are still taken
+                             * by the lower row index); 0: brute force over all rows */
 } ksg_option;
 int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
 
