@@ -197,3 +197,21 @@ def test_window_search_matches_oracle(lib, ctx, case):
         xs = p.x if q == 0 else p.x[perms[q - 1]]
         ref = ksg2_cmi(xs, p.y, p.z, p.k)
         assert abs(got[1][q] - ref) <= tol(ref), (case, q, got[1][q], ref)
+
+
+def test_mixed_window_and_brute_force_batch(lib, ctx):
+    """One algorithm-2 batch whose problems split between the window search (k <= 4, N >= 2048,
+    a Z column), the brute-force kernel (k = 8; N < 2048; no Z) and several column counts, so
+    that its launches run side by side on the auxiliary streams: every estimate equals the
+    oracle's."""
+    specs = [(2500, (1, 1, 2), 4), (2300, (1, 1, 2), 8), (1500, (1, 2, 1), 4), (2400, (2, 1, 3), 3),
+             (2200, (1, 1, 0), 4), (2600, (1, 1, 1), 2)]
+    probs, data = [], []
+    for i, (n, dims, k) in enumerate(specs):
+        p = workloads.random_problem(1800 + i, n, *dims, k)
+        data.append(p)
+        probs.append(lib.Problem(soa(p.x), soa(p.y), soa(p.z), k))
+    out = ctx.cmi_batch(probs).cpu().numpy()
+    for i, p in enumerate(data):
+        ref = ksg2_cmi(p.x, p.y, p.z, p.k)
+        assert abs(out[i] - ref) <= tol(ref), (i, out[i], ref)
