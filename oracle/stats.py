@@ -19,9 +19,10 @@ gives no formulas; the readings taken here are:
   the test is significant; stop at the first non-significant step or when
   the pool is empty;
 * omnibus: I(selected source candidates ; Y | selected target-past
-  candidates), surrogates permute the rows of the whole source block;
-* the conditioning set is capped at 14 columns (16 dimensions with X and Y):
-  a selection stops when it is full.
+  candidates), surrogates permute the rows of the whole source block.
+
+The selection has no size limit here: the paper stops only on the test.
+Tests bound the number of steps with ``max_steps``.
 
 The paper's network paragraph also names bivariate and multivariate
 variants and post-selection statistics without defining them; the readings
@@ -73,8 +74,6 @@ __all__ = [
     "max_statistic_sequential",
     "sequential_final_test",
 ]
-
-MAX_COND = 14  # conditioning columns: 16 dimensions with X and Y
 
 
 def embed(data, target: int, max_lag: int):
@@ -160,7 +159,7 @@ def greedy_select(cand, y, k: int, perms, alpha: float = 0.05, max_steps: int | 
     pool = list(range(cand.shape[0])) if pool is None else list(pool)
     selected = [] if selected is None else list(selected)
     steps, tables = [], []
-    while pool and len(selected) < MAX_COND and (max_steps is None or len(steps) < max_steps):
+    while pool and (max_steps is None or len(steps) < max_steps):
         cmis = _step_cmis(cand, y, [cand[s] for s in selected], pool, perms, k, estimator)
         ms = max_statistic(cmis, alpha)
         steps.append(ms)

@@ -18,7 +18,7 @@ from scipy.spatial import cKDTree
 import workloads
 from oracle.harmonic import harmonic, harmonic_exact, harmonic_table
 from oracle.ksg import (ksg_cmi, ksg_cmi_exact, ksg_counts, ksg_counts_loops,
-                        ksg_point_counts)
+                        ksg_point_counts, local_terms)
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -79,6 +79,33 @@ def test_worked_example_z_empty_is_ksg_mi():
     n, k = 6, g["k"]
     mi = special.digamma(k) + special.digamma(n) - np.mean(special.digamma(nx + 1) + special.digamma(ny + 1))
     assert abs(ksg_cmi(x, y, None, k) - mi) < 1e-14
+
+
+def test_local_terms_worked_example():
+    """Pointwise values of the worked example (hand fractions in the fixture), with and without
+    Z, from the oracle's own counts; their mean is the estimate."""
+    g = _load("ksg_tiny_ties.json")
+    x, y, z = (np.array(g[c], np.float32) for c in "xyz")
+    for zz, ref in ((z, g), (None, g["z_empty"])):
+        _, nxz, nyz, nz = ksg_counts(x, y, zz, g["k"])
+        loc = local_terms(6, g["k"], nxz, nyz, nz)
+        want = [Fraction(v, ref["local_den"]) for v in ref["local_num"]]
+        for got, w in zip(loc, want):
+            assert abs(got - float(w)) <= 4e-16 * max(1.0, abs(float(w))), (got, w)
+        assert sum(want) / 6 == Fraction(ref["cmi_num"], ref["cmi_den"])
+        assert abs(math.fsum(loc) / 6 - ksg_cmi(x, y, zz, g["k"])) <= 1e-15
+
+
+def test_local_terms_mean_is_the_estimate():
+    """On random data the pointwise values average to the estimate (summation-order rounding
+    only), and each is psi(k) - psi(n_xz+1) - psi(n_yz+1) + psi(n_z+1) with scipy's digamma."""
+    for seed, dims, k in ((31, (1, 1, 2), 4), (32, (2, 1, 0), 3), (33, (1, 2, 3), 8)):
+        p = workloads.random_problem(seed, 300, *dims, k)
+        _, nxz, nyz, nz = ksg_counts(p.x, p.y, p.z, k)
+        loc = local_terms(300, k, nxz, nyz, nz)
+        assert abs(math.fsum(loc) / 300 - ksg_cmi(p.x, p.y, p.z, k)) <= 1e-14
+        ref = special.digamma(k) - special.digamma(nxz + 1) - special.digamma(nyz + 1) + special.digamma(nz + 1)
+        assert np.max(np.abs(loc - ref)) <= 1e-12
 
 
 def test_fp32_discriminator():

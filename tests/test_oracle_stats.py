@@ -117,6 +117,31 @@ def test_omnibus():
     assert omnibus_test(cand, y, [6], 3, 2, 4, perms) is None
 
 
+def test_omnibus_permutes_the_source_block_jointly():
+    """Two identical source columns stay identical under a joint row permutation, and a
+    duplicated column leaves every max-norm distance unchanged: so every surrogate of the
+    two-column source block equals the one-column surrogate under the same permutation.
+    Permuting the columns separately would pull the copies apart and change the values."""
+    g = workloads.rng(17)
+    n = 160
+    zt = g.standard_normal(n)
+    src = g.standard_normal(n)
+    yv = 0.8 * src + 0.4 * zt + 0.3 * g.standard_normal(n)
+    # max_lag 1, variables: 0 = target's past (Z), 1 and 2 = two copies of the source
+    cand = np.stack([zt, src, src]).astype(np.float32)
+    y = yv.astype(np.float32)
+    perms = workloads.permutations(n, 12, seed=18)
+    tab, ms = omnibus_test(cand, y, [1, 2, 0], target=0, max_lag=1, k=4, perms=perms)
+    z = cand[0][:, None]
+    assert tab[0, 0] == ksg_cmi(cand[1], y, z, 4)
+    for p in range(perms.shape[0]):
+        assert tab[0, p + 1] == ksg_cmi(cand[1][perms[p]], y, z, 4), p
+    # a column-wise permutation (different rows for the two copies) gives other values
+    split = np.stack([cand[1][perms[0]], cand[2][perms[1]]], axis=1)
+    assert ksg_cmi(split, y, z, 4) != tab[0, 1]
+    assert ms.significant
+
+
 # ---- selection modes, min-statistic pruning, FDR (readings in oracle.stats) ----
 
 def _copy_chain(seed):
