@@ -157,7 +157,7 @@ def c4_dataset(ctx, plan, log=print):
         data = torch.from_numpy(net.data).cuda()
         cand, y = ctx.embed(data, target=target, max_lag=MAX_LAG)
         perms = torch.from_numpy(workloads.permutations(y.shape[0], P, seed=seed + 60_000)).cuda()
-        f, t, o, steps, _ = greedy_path_examples(ctx, cand, y, perms, _subsets_for(g), k=K)
+        f, t, o, steps, _, _ = greedy_path_examples(ctx, cand, y, perms, _subsets_for(g), k=K)
         parts.append((f, t, o))
         log(f"dataset: {i + 1}/{len(plan)} paths, {sum(p[0].shape[0] for p in parts)} examples, "
             f"{time.perf_counter() - t0:.1f} s")

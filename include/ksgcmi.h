@@ -36,7 +36,9 @@
  *  - ksg_last_error(ctx) describes the last failure on that context.
  *
  * Limits: 1 <= k <= 16, N > k, N <= 2^31 - 1024, d_x >= 1, d_y >= 1, d_z >= 0,
- * d_x + d_y + d_z <= 16.
+ * d_x + d_y + d_z <= 32 (<= 16 under KSG algorithm 2).  Problems of up to 16 columns run
+ * kernels compiled per column count; 17..32 columns run one brute-force kernel compiled for 32
+ * columns, or the grouped kernels when d_x = d_y = 1 and several problems share Y and Z.
  */
 #ifndef KSGCMI_H
 #define KSGCMI_H
@@ -58,7 +60,7 @@ typedef enum ksg_status {
   KSG_EBUFSMALL = 7    /* caller-provided output capacity too small (needed size reported) */
 } ksg_status;
 
-#define KSG_MAX_DIMS 16
+#define KSG_MAX_DIMS 32
 #define KSG_MAX_K 16
 
 typedef struct ksg_ctx ksg_ctx;
@@ -297,8 +299,11 @@ int ksg_greedy_step(ksg_ctx* ctx, const float* cand, const float* y, int64_t N, 
  * I(selected sources ; Y | selected target past), surrogates permuting the
  * source block rows.
  *
- * The conditioning set holds at most 14 columns (16 dimensions with X and Y); a selection
- * that fills it stops.
+ * The conditioning set holds at most max_cond columns (0: the column limit less X and Y, i.e.
+ * 30, or 14 under KSG algorithm 2).  When a step includes a candidate and the next step would
+ * need more conditioning columns than that, the selection ends with truncated = 1: the paper's
+ * statistical stop (a non-significant test or an empty pool) was not reached.  max_steps, when
+ * it ends the loop, does not set truncated.
  *
  * Variants named beside multivariate TE in the same paragraph (readings, the paper defines
  * neither): KSG_MODE_MULTIVARIATE_MI: the pool without the target's own past;
@@ -344,6 +349,7 @@ typedef struct ksg_select_opts {
   int32_t prune;     /* 1: min-statistic pruning of the selected sources */
   int32_t sequential; /* 1: sequential max-statistic test of the kept sources (after pruning;
                        * skipped when the omnibus test ran and was not significant) */
+  int32_t max_cond;   /* 0 = the library's limit; else at most this many conditioning columns */
 } ksg_select_opts;
 
 enum { KSG_MODE_MULTIVARIATE_TE = 0, KSG_MODE_BIVARIATE_TE = 1, KSG_MODE_MULTIVARIATE_MI = 2 };
@@ -385,6 +391,9 @@ typedef struct ksg_parent_set {
   int32_t n_seq_removed;
   int32_t* seq_removed;
   double* seq_pval;
+  /* 1: the inclusion loop ended at the conditioning limit (max_cond) after a significant step,
+   * not at a non-significant test or an empty pool; 0 otherwise. */
+  int32_t truncated;
 } ksg_parent_set;
 
 /* data: device FP32 [n_trials][n_vars][T].  out: host struct.

@@ -11,7 +11,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libksgcmi.so")
 
-KSG_MAX_DIMS = 16
+KSG_MAX_DIMS = 32
 KSG_MAX_K = 16
 MLP_NPARAMS = 5378
 MLP_NFEAT = 16
@@ -52,7 +52,7 @@ class _SelectOpts(C.Structure):
                 ("omnibus", C.c_int32), ("alpha", C.c_double), ("perms", C.c_void_p),
                 ("learned", C.c_void_p), ("margin_lo", C.c_double), ("margin_hi", C.c_double),
                 ("judge", C.c_int32), ("max_steps", C.c_int32), ("mode", C.c_int32), ("prune", C.c_int32),
-                ("sequential", C.c_int32)]
+                ("sequential", C.c_int32), ("max_cond", C.c_int32)]
 
 
 class _ParentSet(C.Structure):
@@ -64,7 +64,7 @@ class _ParentSet(C.Structure):
                 ("step_capacity", C.c_int32), ("step_tobs", C.c_void_p), ("step_pred", C.c_void_p),
                 ("step_verdict", C.c_void_p), ("step_plain", C.c_void_p), ("n_pruned", C.c_int32),
                 ("pruned", C.c_void_p), ("n_seq_removed", C.c_int32), ("seq_removed", C.c_void_p),
-                ("seq_pval", C.c_void_p)]
+                ("seq_pval", C.c_void_p), ("truncated", C.c_int32)]
 
 
 def _load():
@@ -373,10 +373,11 @@ class Context:
                        alpha: float = 0.05, omnibus: bool = False, learned: "ThresholdNet" = None,
                        margin_lo: float = 1.0, margin_hi: float = 1.0, judge: bool = False,
                        max_steps: int = 0, capacity: int = 64, mode: str = "mte",
-                       prune: bool = False, sequential: bool = False) -> dict:
+                       prune: bool = False, sequential: bool = False, max_cond: int = 0) -> dict:
         """Parents of one target.  mode: "mte" (multivariate TE), "bte" (bivariate TE) or "mmi"
         (multivariate MI); prune: min-statistic pruning of the selected sources; sequential:
-        sequential max-statistic test of the kept sources."""
+        sequential max-statistic test of the kept sources; max_cond: conditioning columns allowed
+        (0 = the library's limit); "truncated" in the result reports a selection that ended at it."""
         import torch
         _check_dtype(data, torch.float32, "data")
         _check_dtype(perms, torch.int32, "perms")
@@ -384,7 +385,7 @@ class Context:
         opts = _SelectOpts(int(k), int(max_lag), int(perms.shape[0]), int(bool(omnibus)), float(alpha),
                            _ptr(perms), learned._h if learned is not None else None, float(margin_lo),
                            float(margin_hi), int(bool(judge)), int(max_steps), MODES[mode], int(bool(prune)),
-                           int(bool(sequential)))
+                           int(bool(sequential)), int(max_cond))
         var = np.zeros(capacity, np.int32)
         lag = np.zeros(capacity, np.int32)
         cmi = np.zeros(capacity, np.float64)
@@ -415,7 +416,7 @@ class Context:
                     omnibus_pval=ps.omnibus_pval, n_cmi=ps.n_cmi,
                     pruned=[int(v) for v in prn[:min(ps.n_pruned, capacity)]],
                     seq_removed=[int(v) for v in srm[:min(ps.n_seq_removed, capacity)]],
-                    seq_pval=spv[:n].tolist(),
+                    seq_pval=spv[:n].tolist(), truncated=bool(ps.truncated),
                     steps=[dict(t_obs=float(s_t[i]), pred=[float(s_p[i, 0]), float(s_p[i, 1])],
                                 verdict=int(s_v[i]), plain=int(s_pl[i]))
                            for i in range(min(ps.n_steps, scap))])

@@ -11,18 +11,21 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libksgcmi.so")
 
-SOURCES = [
+SOURCES = [  # longest compiles first, so that the parallel build ends early
+    "ksg_window.hip",
+    "ksg_alg2.hip",
     "ksg_search_kp5.hip",
     "ksg_search_kp9.hip",
     "ksg_search_kp17.hip",
+    "ksg_window_alg2.hip",
+    "ksg_search_wide.hip",
+    "ksg_group_wide_kp5.hip",
+    "ksg_group_wide_kp9.hip",
     "ksg_group_kp5_g8.hip",
     "ksg_group_kp5_g16.hip",
     "ksg_group_kp9_g8.hip",
     "ksg_group_kp9_g16.hip",
     "ksg_yzcount.hip",
-    "ksg_alg2.hip",
-    "ksg_window.hip",
-    "ksg_window_alg2.hip",
     "ksg_misc.hip",
     "ksg_api.hip",
     "greedy.hip",

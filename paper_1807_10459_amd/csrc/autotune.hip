@@ -81,7 +81,7 @@ extern "C" int ksg_autotune(ksg_ctx* c, int64_t n, const char* cache_path, int32
   bool cached = cache_path && load_cache(c, cache_path);
   if (!cached) {
     const int n_x = 32;                       // X columns (one step's candidates x rounds)
-    const int cols = n_x + 1 + (kMaxDims - 2);  // X..., Y, Z1..Z14
+    const int cols = n_x + 1 + kGroupMaxM16;  // X..., Y, Z1..Z14 (larger m always use groups of 8)
     int st = c->reserve(c->embed, sizeof(float) * (size_t)cols * n, "tuning data");
     if (st) return st;
     float* d = (float*)c->embed.ptr;
@@ -106,7 +106,7 @@ extern "C" int ksg_autotune(ksg_ctx* c, int64_t n, const char* cache_path, int32
     c->algorithm = 1;  // the group size only matters to algorithm 1 (algorithm 2 is not grouped)
     for (int t = 0; t < 2; ++t) {
       const int k = t == 0 ? 4 : 8;
-      for (int m = 0; m <= 14; ++m) {
+      for (int m = 0; m <= kGroupMaxM16; ++m) {
         std::vector<Problem> probs(n_x);
         for (int i = 0; i < n_x; ++i) {
           Problem& q = probs[i];

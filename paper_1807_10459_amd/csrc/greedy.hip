@@ -77,6 +77,7 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   if (n_vars < 1 || n_trials < 1 || T <= o->max_lag || target < 0 || target >= n_vars)
     return c->fail(KSG_EINVAL, "select_parents: bad data shape");
   if (out->capacity < 0) return c->fail(KSG_EINVAL, "select_parents: negative capacity");
+  if (o->max_cond < 0) return c->fail(KSG_EINVAL, "select_parents: max_cond must be >= 0");
   if (o->learned && !(o->margin_lo >= 0 && o->margin_hi >= 0))
     return c->fail(KSG_EINVAL, "select_parents: margins must be >= 0");
   if (o->mode < KSG_MODE_MULTIVARIATE_TE || o->mode > KSG_MODE_MULTIVARIATE_MI || (o->prune != 0 && o->prune != 1) ||
@@ -126,6 +127,7 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   double* d_cmi = (double*)c->cmi.ptr;
 
   out->n = 0;
+  out->truncated = 0;
   out->n_pruned = 0;
   out->n_steps = 0;
   out->n_fallback = 0;
@@ -148,9 +150,18 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   std::vector<int> incl;       // every included candidate, in order
   std::vector<double> incl_t;  // t_obs and p-value of its step
   std::vector<double> incl_p;
+  // The conditioning set may hold at most cond_limit columns: the library's column limit less X
+  // and Y (30; 14 under KSG algorithm 2), or the caller's smaller max_cond.  A selection whose
+  // next step would need more stops there with truncated = 1: its last test was significant,
+  // so the statistical stop was not reached.
+  const int lib_cond = (c->algorithm == 2 ? kMaxDimsCompiled : KSG_MAX_DIMS) - 2;
+  const int cond_limit = o->max_cond > 0 ? std::min(o->max_cond, lib_cond) : lib_cond;
   auto include_loop = [&]() -> int {
   while (!s.pool.empty() && (o->max_steps <= 0 || out->n_steps < o->max_steps)) {
-    if (2 + (int)s.selected.size() > KSG_MAX_DIMS) break;  // conditioning set at the dimension limit
+    if ((int)s.selected.size() > cond_limit) {
+      out->truncated = 1;
+      break;
+    }
     const int cands = (int)s.pool.size();
     int decision = -1;  // 1 include, 0 stop
     double t_obs = 0, pval = -1;
@@ -316,7 +327,7 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   if (o->omnibus) {
     std::vector<int> src, tgt;
     for (int cidx : s.selected) (cidx / s.L == target ? tgt : src).push_back(cidx);
-    if (!src.empty() && (int)(src.size() + 1 + tgt.size()) <= KSG_MAX_DIMS) {
+    if (!src.empty() && (int)(src.size() + 1 + tgt.size()) <= lib_cond + 2) {
       std::vector<Problem> probs(s.P + 1);
       for (int p = 0; p <= s.P; ++p) {
         Problem& q = probs[p];
@@ -413,7 +424,8 @@ extern "C" int ksg_greedy_step(ksg_ctx* c, const float* cand, const float* y, in
   if (!cand || !y || !pool || (n_cond > 0 && !cond) || !cmi_out || !result || (n_perm > 0 && !perms))
     return c->fail(KSG_EINVAL, "ksg_greedy_step: null argument");
   if (n_pool < 1 || n_cond < 0 || 2 + n_cond > KSG_MAX_DIMS || n_perm < 1 || n_perm > 4096)
-    return c->fail(KSG_EINVAL, "ksg_greedy_step: need n_pool >= 1, 0 <= n_cond <= 14, 1 <= n_perm <= 4096");
+    return c->fail(KSG_EINVAL, "ksg_greedy_step: need n_pool >= 1, 0 <= n_cond <= %d, 1 <= n_perm <= 4096",
+                   KSG_MAX_DIMS - 2);
   for (int i = 0; i < n_pool; ++i)
     if (pool[i] < 0) return c->fail(KSG_EINVAL, "ksg_greedy_step: negative candidate index");
   for (int i = 0; i < n_cond; ++i)

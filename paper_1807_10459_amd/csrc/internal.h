@@ -6,14 +6,20 @@
 
 namespace ksg {
 
-constexpr int kMaxDims = 16;
+constexpr int kMaxDims = 32;        // columns of one problem (X + Y + Z)
+constexpr int kMaxDimsCompiled = 16; // column counts with kernels compiled per count (brute force,
+                                     // key-ordered windows, algorithm 2)
+constexpr int kWideDims = 32;        // 16 < D <= 32: one brute-force kernel compiled for 32 columns,
+                                     // the columns beyond D being zero columns in Z
+constexpr int kGroupMaxM = kMaxDims - 2;  // conditioning columns of grouped problems
+constexpr int kGroupMaxM16 = 14;          // ... with 16 problems per group
 constexpr int kTileQ = 256;       // queries per work item (4 waves x 64 lanes, one query per lane)
 constexpr int kPad = 64;          // column length is padded to a multiple of this with +inf
 constexpr int kMaxK = 16;
 constexpr int kWindowMinN = 2048;  // smallest N searched with key-ordered windows (single problems)
 
 // One CMI problem as the search kernel sees it.  Columns are ordered X..., Y..., Z...,
-// each padded with +inf rows up to n_pad.  128 + 96 bytes, 16-byte aligned.
+// each padded with +inf rows up to n_pad.  256 + 96 bytes, 16-byte aligned.
 struct alignas(16) ProbDesc {
   const float* col[kMaxDims];
   int32_t n;          // points
@@ -84,7 +90,8 @@ struct WorkItem {
 };
 
 // A column copy job for the pack kernel: dst[i] = src[perm ? perm[i] : i] (i < n),
-// +inf for n <= i < n_pad.
+// +inf for n <= i < n_pad.  src == nullptr: dst[i] = 0 for i < n, +inf for n <= i < n_pad
+// (the zero columns that fill a wide problem up to kWideDims columns).
 struct PackJob {
   const float* src;
   const int32_t* perm;
@@ -105,7 +112,7 @@ inline int shape_id(int dx, int dy, int dz) {
   if (dx == 1 && dy == 1) pair = 0;
   else if (dx == 1 && dy == 2) pair = 1;
   else if (dx == 2 && dy == 2) pair = 2;
-  if (pair < 0 || dz > kFastMaxDz || dx + dy + dz > kMaxDims) return kGenericShape;
+  if (pair < 0 || dz > kFastMaxDz || dx + dy + dz > kMaxDimsCompiled) return kGenericShape;
   return pair * (kFastMaxDz + 1) + dz;
 }
 

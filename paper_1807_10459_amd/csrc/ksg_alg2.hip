@@ -240,7 +240,7 @@ const void* alg2_kernels[3][15] = {KSG_A2_ROW(5), KSG_A2_ROW(9), KSG_A2_ROW(17)}
 hipError_t launch_ksg_alg2(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                            const double* d_htab, double* d_partials, int D, int kp, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
-  if (D < 2 || D > kMaxDims || (kp != 5 && kp != 9 && kp != 17)) return hipErrorInvalidValue;
+  if (D < 2 || D > kMaxDimsCompiled || (kp != 5 && kp != 9 && kp != 17)) return hipErrorInvalidValue;
   const void* fn = alg2_kernels[kp == 5 ? 0 : (kp == 9 ? 1 : 2)][D - 2];
   const ProbDesc* a0 = d_desc;
   const WorkItem* a1 = d_items;

@@ -289,6 +289,9 @@ int ksg_ctx::validate(const Problem& p, int index) {
                 index, p.dx, p.dy, p.dz, KSG_MAX_DIMS);
   if (p.k < 1 || p.k > KSG_MAX_K)
     return fail(KSG_EINVAL, "problem %d: k=%d outside [1, %d]", index, p.k, KSG_MAX_K);
+  if (algorithm == 2 && D > kMaxDimsCompiled)
+    return fail(KSG_EINVAL, "problem %d: %d columns; KSG algorithm 2 supports at most %d", index, D,
+                kMaxDimsCompiled);
   if (p.n > (int64_t)INT32_MAX - 1024)
     return fail(KSG_EINVAL, "problem %d: N=%lld too large", index, (long long)p.n);
   if (p.n <= p.k)
@@ -342,7 +345,7 @@ std::vector<WorkItem> order_items(const std::vector<Unit>& units) {
 // Problems that share Y, Z, N and k and differ only in a 1-D X column can be searched as a
 // group (Y/Z distances computed once per pair for the whole group).
 static bool groupable(const Problem& p) {
-  if (p.dx != 1 || p.dy != 1 || p.dz > kMaxDims - 2 || p.k + 1 > 9) return false;
+  if (p.dx != 1 || p.dy != 1 || p.dz > kGroupMaxM || p.k + 1 > 9) return false;
   if (p.eps_out || p.counts_out || p.local_out) return false;
   for (int a = 1; a < 2 + p.dz; ++a)
     if (p.perm[a]) return false;
@@ -378,7 +381,8 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       const std::vector<int>& members = kv.second;
       if (members.size() < 2) continue;
       const int m = probs[members[0]].dz;
-      const int G = group_size > 0 ? group_size : tuned_group_size(m, probs[members[0]].k);
+      int G = group_size > 0 ? group_size : tuned_group_size(m, probs[members[0]].k);
+      if (m > kGroupMaxM16) G = 8;  // the wider conditioning sets are compiled for groups of 8
       for (size_t s = 0; s < members.size(); s += G) {
         std::vector<int> g(members.begin() + s, members.begin() + std::min(members.size(), s + (size_t)G));
         for (int i : g) group_of[i] = (int)groups.size();
@@ -396,7 +400,9 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     std::map<std::pair<const float*, int64_t>, int> by_key;
     for (int i = 0; i < np; ++i) {
       const Problem& p = probs[i];
-      if (group_of[i] >= 0 || p.k + 1 > 5 || p.n < kWindowMinN || p.dz < 1) continue;
+      if (group_of[i] >= 0 || p.k + 1 > 5 || p.n < kWindowMinN || p.dz < 1 ||
+          p.dx + p.dy + p.dz > kMaxDimsCompiled)
+        continue;
       if (p.eps_out || p.counts_out || p.local_out) continue;
       int a_key = -1;
       for (int a = p.dx + p.dy; a < p.dx + p.dy + p.dz && a_key < 0; ++a)
@@ -462,6 +468,35 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       col_off[i][a] = it->second;
     }
   }
+  // ---- wide problems (16 < D <= 32, not grouped): searched as problems of kWideDims columns,
+  // their Z filled up with a zero column of the pool (exact: see ksg_search_wide.hip).  The
+  // column is zero in the N rows and +inf in the padding rows, like every column, so that the
+  // padding never enters a count: one per distinct N. ----
+  std::vector<char> wide(np, 0);
+  std::vector<int64_t> zero_off(np, -1);
+  bool any_wide = false;
+  {
+    std::map<int64_t, int64_t> zero_of_n;
+    for (int i = 0; i < np; ++i) {
+      const Problem& p = probs[i];
+      wide[i] = group_of[i] < 0 && p.dx + p.dy + p.dz > kMaxDimsCompiled;
+      if (!wide[i]) continue;
+      any_wide = true;
+      auto it = zero_of_n.find(p.n);
+      if (it == zero_of_n.end()) {
+        it = zero_of_n.emplace(p.n, pool_floats).first;
+        PackJob j;
+        std::memset(&j, 0, sizeof j);
+        j.src = nullptr;                                // zeros, +inf padding
+        j.dst = reinterpret_cast<float*>(pool_floats);  // offset for now
+        j.n = (int)p.n;
+        j.n_pad = (int)round_up(p.n, kPad);
+        jobs.push_back(j);
+        pool_floats += j.n_pad;
+      }
+      zero_off[i] = it->second;
+    }
+  }
   // key orders of the window sets (int32, n_pad entries each) follow the packed columns
   std::vector<int64_t> wsigma_off(wsets.size());
   for (size_t w = 0; w < wsets.size(); ++w) {
@@ -525,6 +560,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   }
   int common_shape = -2;
   int kp = 5;
+  int wide_kp = 5;
   for (int r = 0; r < np; ++r) {
     const int i = order[r];
     const Problem& p = probs[i];
@@ -542,11 +578,13 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       }
       d.col[a] = col_off[i][src] < 0 ? p.col[src] : pool_base + col_off[i][src];
     }
+    if (wide[i])
+      for (int a = D; a < kWideDims; ++a) d.col[a] = pool_base + zero_off[i];
     d.n = (int)p.n;
     d.n_pad = (int)round_up(p.n, kPad);
     d.dx = dx;
     d.dy = dy;
-    d.dz = p.dz;
+    d.dz = wide[i] ? kWideDims - dx - dy : p.dz;
     d.k = p.k;
     d.n_tiles = n_tiles_of(i);
     d.eps_out = p.eps_out;
@@ -565,6 +603,10 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     } else if (win_of[i] >= 0) {
       d.part_base = part;
       part += d.n_tiles;
+    } else if (wide[i]) {
+      d.part_base = part;
+      part += d.n_tiles;
+      wide_kp = std::max(wide_kp, p.k + 1 <= 5 ? 5 : (p.k + 1 <= 9 ? 9 : 17));
     } else {
       d.part_base = part;
       part += d.n_tiles;
@@ -605,10 +647,13 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   } else {
     std::vector<Unit> units;
     for (int r = 0; r < np; ++r)
-      if (group_of[order[r]] < 0 && win_of[order[r]] < 0) units.push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
+      if (group_of[order[r]] < 0 && win_of[order[r]] < 0 && !wide[order[r]])
+        units.push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
     for (const Unit& u : units) plain_cost += u.cost;
     items = order_items(units);
   }
+  // items before the window and wide segments (brute-force items, or the algorithm-2 segments)
+  const int n_plain_items = (int)items.size();
   // window problems: one launch per column count, after the other ungrouped items
   std::vector<Segment> wsegments;
   {
@@ -625,8 +670,17 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       items.insert(items.end(), seg.begin(), seg.end());
     }
   }
-  // items before the window segments (brute-force items, or the algorithm-2 segments)
-  const int n_plain_items = wsegments.empty() ? (int)items.size() : wsegments[0].off;
+  // wide problems: one launch of the kernel compiled for kWideDims columns
+  Segment wide_seg{kWideDims, wide_kp, (int)items.size(), 0, 0.0};
+  if (any_wide) {
+    std::vector<Unit> units;
+    for (int r = 0; r < np; ++r)
+      if (wide[order[r]]) units.push_back(Unit{r, descs[r].n_tiles, cost(order[r])});
+    std::vector<WorkItem> seg = order_items(units);
+    for (const Unit& u : units) wide_seg.cost += u.cost;
+    wide_seg.count = (int)seg.size();
+    items.insert(items.end(), seg.begin(), seg.end());
+  }
 
   // ---- groups: descriptors, launch chunks, Y/Z count descriptors, work items ----
   // Groups of one (m, G, KP) class run as chunks of consecutive groups, each chunk three
@@ -842,7 +896,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   // stream, so that launches too small to fill the device run side by side.  Grouped chunks
   // stay on the context's stream.
   struct Launch {
-    int kind;  // 0 brute-force items, 1 window segment, 2 algorithm-2 segment
+    int kind;  // 0 brute-force items, 1 window segment, 2 algorithm-2 segment, 3 wide problems
     int seg;
     double cost;
   };
@@ -853,6 +907,7 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
     launches.push_back(Launch{0, 0, plain_cost});
   }
   for (size_t g = 0; g < wsegments.size(); ++g) launches.push_back(Launch{1, (int)g, wsegments[g].cost});
+  if (wide_seg.count > 0) launches.push_back(Launch{3, 0, wide_seg.cost});
   const bool fork = launches.size() + (chunks.empty() ? 0 : 1) > 1;
   std::vector<hipStream_t> launch_stream(launches.size(), stream);
   bool aux_used[ksg_ctx::kAuxStreams] = {false, false, false};
@@ -887,7 +942,11 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
       const Launch& L = launches[li];
       const hipStream_t ls = launch_stream[li];
       if ((st = span_begin(ls))) return st;
-      if (L.kind == 2) {
+      if (L.kind == 3) {
+        KSG_HIP(this, launch_ksg_search((const ProbDesc*)desc.ptr, d_items + wide_seg.off, wide_seg.count,
+                                        (const double*)htab.ptr, (double*)partials.ptr, kGenericShape + kWideDims,
+                                        wide_seg.kp, ls));
+      } else if (L.kind == 2) {
         const Segment& g = segments[L.seg];
         KSG_HIP(this, launch_ksg_alg2((const ProbDesc*)desc.ptr, d_items + g.off, g.count, (const double*)htab.ptr,
                                       (double*)partials.ptr, g.D, g.kp, ls));

@@ -22,11 +22,16 @@ extern const void* group_radius_kernels_kp9_g8[15];
 extern const void* group_radius_kernels_kp9_g16[15];
 extern const void* group_xcount_kernels_g8[15];
 extern const void* group_xcount_kernels_g16[15];
-extern const void* yzcount_kernels[15];
+extern const void* yzcount_kernels[kGroupMaxM + 1];
+extern const void* group_radius_kernels_kp5_g8_wide[16];
+extern const void* group_radius_kernels_kp9_g8_wide[16];
+extern const void* group_xcount_kernels_g8_wide[16];
+extern const void* search_kernels_wide[3];
 
 // ------------------------------------------------------------------ packing
 
-// grid.x: chunks of 1024 rows, grid.y: jobs (strided).  dst[i] = src[perm[i]] or src[i]; pad +inf.
+// grid.x: chunks of 1024 rows, grid.y: jobs (strided).  dst[i] = src[perm[i]] or src[i]; pad +inf;
+// a job without a source writes a zero column (zeros in the n rows, +inf padding).
 // A gather index outside [0, n) is never dereferenced: the row becomes NaN and bit 1 of
 // *flag is set (the finite check then reports the batch as invalid).
 __global__ __launch_bounds__(256) void pack_kernel(const PackJob* __restrict__ jobs, int n_jobs,
@@ -35,6 +40,14 @@ __global__ __launch_bounds__(256) void pack_kernel(const PackJob* __restrict__ j
     const PackJob job = jobs[jb];
     const int base = blockIdx.x * 1024;
     if (base >= job.n_pad) continue;
+    if (!job.src) {  // a zero column (wide problems): zeros in the n rows, +inf padding
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = base + r * 256 + threadIdx.x;
+        if (i < job.n_pad) job.dst[i] = i < job.n ? 0.0f : INFINITY;
+      }
+      continue;
+    }
     bool bad = false;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -281,9 +294,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(const ProbDesc* __restric
 }
 
 static const void* pick_search_kernel(int shape, int kp) {
+  if (shape == kGenericShape + kWideDims) return search_kernels_wide[kp <= 5 ? 0 : (kp <= 9 ? 1 : 2)];
   const void* const* table = kp <= 5 ? search_kernels_kp5 : (kp <= 9 ? search_kernels_kp9 : search_kernels_kp17);
   if (shape >= 0 && shape < 39) return table[shape];
-  if (shape >= kGenericShape + 2 && shape <= kGenericShape + kMaxDims) return table[40 + shape - kGenericShape - 2];
+  if (shape >= kGenericShape + 2 && shape <= kGenericShape + kMaxDimsCompiled)
+    return table[40 + shape - kGenericShape - 2];
   return table[39];
 }
 
@@ -304,23 +319,31 @@ hipError_t launch_ksg_group_radius(const float* base, const GroupDesc* d_gdesc, 
                                    int n_items, float* E, int m, int G, int kp,
                                    unsigned long long* d_work, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
-  if (m < 0 || m > 14 || (G != 8 && G != 16) || (kp != 5 && kp != 9)) return hipErrorInvalidValue;
-  const void* const* table = kp == 5 ? (G == 8 ? group_radius_kernels_kp5_g8 : group_radius_kernels_kp5_g16)
-                                     : (G == 8 ? group_radius_kernels_kp9_g8 : group_radius_kernels_kp9_g16);
+  // m <= 14: any group size; m = 15..30: 8 problems per group only
+  if (m < 0 || m > kGroupMaxM || (G != 8 && G != 16) || (kp != 5 && kp != 9) || (G == 16 && m > kGroupMaxM16))
+    return hipErrorInvalidValue;
+  const void* fn;
+  if (m > kGroupMaxM16) {
+    fn = (kp == 5 ? group_radius_kernels_kp5_g8_wide : group_radius_kernels_kp9_g8_wide)[m - kGroupMaxM16 - 1];
+  } else {
+    const void* const* table = kp == 5 ? (G == 8 ? group_radius_kernels_kp5_g8 : group_radius_kernels_kp5_g16)
+                                       : (G == 8 ? group_radius_kernels_kp9_g8 : group_radius_kernels_kp9_g16);
+    fn = table[m];
+  }
   const float* a0 = base;
   const GroupDesc* a1 = d_gdesc;
   const WorkItem* a2 = d_items;
   float* a3 = E;
   unsigned long long* a4 = d_work;
   void* args[] = {&a0, &a1, &a2, &a3, &a4};
-  return hipLaunchKernel(table[m], dim3(n_items), dim3(kTileQ), args, 0, stream);
+  return hipLaunchKernel(fn, dim3(n_items), dim3(kTileQ), args, 0, stream);
 }
 
 hipError_t launch_ksg_yzcount(const float* base, const YZDesc* d_ydesc, const WorkItem* d_items,
                               int n_items, const float* E, double* T, const double* d_htab, int m,
                               unsigned long long* d_work, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
-  if (m < 0 || m > 14) return hipErrorInvalidValue;
+  if (m < 0 || m > kGroupMaxM) return hipErrorInvalidValue;
   const float* a0 = base;
   const YZDesc* a1 = d_ydesc;
   const WorkItem* a2 = d_items;
@@ -337,8 +360,9 @@ hipError_t launch_ksg_group_xcount(const float* base, const GroupDesc* d_gdesc, 
                                    double* d_partials, int m, int G, unsigned long long* d_work,
                                    hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
-  if (m < 0 || m > 14 || (G != 8 && G != 16)) return hipErrorInvalidValue;
-  const void* const* table = G == 8 ? group_xcount_kernels_g8 : group_xcount_kernels_g16;
+  if (m < 0 || m > kGroupMaxM || (G != 8 && G != 16) || (G == 16 && m > kGroupMaxM16)) return hipErrorInvalidValue;
+  const void* fn = m > kGroupMaxM16 ? group_xcount_kernels_g8_wide[m - kGroupMaxM16 - 1]
+                                    : (G == 8 ? group_xcount_kernels_g8 : group_xcount_kernels_g16)[m];
   const float* a0 = base;
   const GroupDesc* a1 = d_gdesc;
   const WorkItem* a2 = d_items;
@@ -348,7 +372,7 @@ hipError_t launch_ksg_group_xcount(const float* base, const GroupDesc* d_gdesc, 
   double* a6 = d_partials;
   unsigned long long* a7 = d_work;
   void* args[] = {&a0, &a1, &a2, &a3, &a4, &a5, &a6, &a7};
-  return hipLaunchKernel(table[m], dim3(n_items), dim3(kTileQ), args, 0, stream);
+  return hipLaunchKernel(fn, dim3(n_items), dim3(kTileQ), args, 0, stream);
 }
 
 hipError_t launch_finalize(const ProbDesc* d_desc, int n_probs, const double* d_partials,

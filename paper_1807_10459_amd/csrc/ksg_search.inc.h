@@ -278,7 +278,7 @@ __device__ __forceinline__ void search_tile_dims(const KSG_AS4 ProbDesc* pd, int
   tile_epilogue(pd, tile, qi, valid, eps, c.xz, c.yz, c.z, dx + dy == D, htab, partials, s_red);
 }
 
-// Generic path: any split of up to kMaxDims dimensions, subspace membership resolved
+// Generic path: any split of up to kMaxDimsCompiled dimensions, subspace membership resolved
 // with wave-uniform selects.  Used for shapes outside the fast table.
 template <int D, int KP>
 __device__ __forceinline__ void search_tile_generic(const KSG_AS4 ProbDesc* pd, int tile,

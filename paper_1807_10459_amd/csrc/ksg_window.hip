@@ -56,7 +56,7 @@ hipError_t launch_window_rank(const float* key, int n, int n_pad, int32_t* sigma
 hipError_t launch_ksg_window(const ProbDesc* d_desc, const WorkItem* d_items, int n_items, const double* d_htab,
                              double* d_partials, int D, int alg, unsigned long long* d_work, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
-  if (D < 2 || D > kMaxDims || (alg != 1 && alg != 2)) return hipErrorInvalidValue;
+  if (D < 2 || D > kMaxDimsCompiled || (alg != 1 && alg != 2)) return hipErrorInvalidValue;
   const ProbDesc* a0 = d_desc;
   const WorkItem* a1 = d_items;
   const double* a2 = d_htab;

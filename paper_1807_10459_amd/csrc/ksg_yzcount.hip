@@ -217,8 +217,12 @@ __global__ __launch_bounds__(kYZThreads) void ksg_yzcount_kernel(const float* __
 }
 
 #define KSG_YZ(M) reinterpret_cast<const void*>(&ksg_yzcount_kernel<M>)
-const void* yzcount_kernels[15] = {KSG_YZ(0),  KSG_YZ(1),  KSG_YZ(2),  KSG_YZ(3), KSG_YZ(4),
-                                   KSG_YZ(5),  KSG_YZ(6),  KSG_YZ(7),  KSG_YZ(8), KSG_YZ(9),
-                                   KSG_YZ(10), KSG_YZ(11), KSG_YZ(12), KSG_YZ(13), KSG_YZ(14)};
+// [m] for m = 0..kGroupMaxM
+const void* yzcount_kernels[kGroupMaxM + 1] = {
+    KSG_YZ(0),  KSG_YZ(1),  KSG_YZ(2),  KSG_YZ(3),  KSG_YZ(4),  KSG_YZ(5),  KSG_YZ(6),  KSG_YZ(7),
+    KSG_YZ(8),  KSG_YZ(9),  KSG_YZ(10), KSG_YZ(11), KSG_YZ(12), KSG_YZ(13), KSG_YZ(14), KSG_YZ(15),
+    KSG_YZ(16), KSG_YZ(17), KSG_YZ(18), KSG_YZ(19), KSG_YZ(20), KSG_YZ(21), KSG_YZ(22), KSG_YZ(23),
+    KSG_YZ(24), KSG_YZ(25), KSG_YZ(26), KSG_YZ(27), KSG_YZ(28), KSG_YZ(29), KSG_YZ(30)};
+static_assert(kGroupMaxM == 30, "one instantiation per conditioning dimension");
 
 }  // namespace ksg

@@ -84,7 +84,8 @@ struct ksg_ctx {
   int64_t last_items = 0;
   int64_t last_groups = 0;
   int tuned_group_size(int m, int k) const {
-    const int t = tuned_g[k <= 4 ? 0 : 1][m < 15 ? m : 14];
+    if (m > ksg::kGroupMaxM16) return 8;  // only groups of 8 are compiled for m > 14
+    const int t = tuned_g[k <= 4 ? 0 : 1][m];
     return t ? t : 8;
   }
   static double algorithmic_ops(const ksg::Problem& p, int ng);

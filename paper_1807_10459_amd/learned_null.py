@@ -17,7 +17,7 @@ from __future__ import annotations
 import dataclasses
 from typing import Iterable, List, Sequence
 
-from ._binding import Context, ThresholdNet
+from ._binding import KSG_MAX_DIMS, Context, ThresholdNet
 
 
 @dataclasses.dataclass
@@ -59,15 +59,16 @@ def build_dataset(ctx: Context, specs: Iterable[StepSpec]):
 
 
 def greedy_path_examples(ctx: Context, cand, y, perms, subsets_for, k: int = 4,
-                         alpha: float = 0.05, max_cond: int = 14):
+                         alpha: float = 0.05, max_cond: int = KSG_MAX_DIMS - 2):
     """Examples from every step of the plain greedy selection on one target.
 
     The plain method is run step by step (ksg_greedy_step: all candidates x surrogates in one
     batched launch, then the max-statistic test), so the examples come from exactly the
     steps -- conditioning sets, candidate pools, observed statistics -- that select_parents
     meets.  subsets_for(n_pool, step) returns the candidate subsets (positions into the pool)
-    to take from each step; the caller owns the randomness.
-    Returns (feats, targets, obs, n_steps, parents).
+    to take from each step; the caller owns the randomness.  max_cond caps the conditioning
+    set as select_parents does; a path that reaches it after a significant step is truncated.
+    Returns (feats, targets, obs, n_steps, parents, truncated).
     """
     import torch
     C = cand.shape[0]
@@ -75,7 +76,11 @@ def greedy_path_examples(ctx: Context, cand, y, perms, subsets_for, k: int = 4,
     cond: List[int] = []
     fs, ts, os_ = [], [], []
     step = 0
-    while pool and len(cond) <= max_cond:
+    truncated = False
+    while pool:
+        if len(cond) > max_cond:
+            truncated = True
+            break
         table, res = ctx.greedy_step(cand, y, pool, cond, perms, k=k, alpha=alpha)
         f, t, o = ctx.null_examples(table, pool, subsets_for(len(pool), step), cand, y, dz=len(cond), k=k)
         fs.append(f)
@@ -87,7 +92,7 @@ def greedy_path_examples(ctx: Context, cand, y, perms, subsets_for, k: int = 4,
         c = pool[res["c_star"]]
         cond.append(c)
         pool.remove(c)
-    return torch.cat(fs), torch.cat(ts), torch.cat(os_), step, cond
+    return torch.cat(fs), torch.cat(ts), torch.cat(os_), step, cond, truncated
 
 
 def train_threshold_net(ctx: Context, feats, targets, init_params, epochs: int = 40,

@@ -223,9 +223,9 @@ def test_errors(lib, ctx):
     with pytest.raises(lib.KsgError) as e:
         ctx.cmi(soa(bad), soa(np.ones((50, 1), np.float32)), None, 4)
     assert e.value.status == 3
-    big = soa(np.zeros((50, 17), np.float32))
+    big = soa(np.zeros((50, 32), np.float32))  # 33 columns with Y
     with pytest.raises(lib.KsgError) as e:
-        ctx.cmi(big, x, None, 4)
+        ctx.cmi(big, soa(np.zeros((50, 1), np.float32)), None, 4)
     assert e.value.status == 1
     # the context stays usable after errors
     p = workloads.random_problem(1, 100, 1, 1, 1, 4)
