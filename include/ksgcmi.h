@@ -205,6 +205,25 @@ int cmi_ksg(ksg_ctx* ctx, const float* x, const float* y, const float* z, int64_
             const int32_t dims[3], int32_t k, double* out_nats);
 
 /* ---------------------------------------------------------------------------
+ * The estimate of cmi_ksg without any allocation, for callers that cannot allocate: code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc.  Arguments as for
+ * cmi_ksg, except out_nats: a DEVICE pointer to one double, written in stream order (the call
+ * returns once the work is queued on the context's stream; nothing synchronises).
+ * Everything beyond the caller's inputs and output lives in one static device array of the
+ * library (under 5 MiB per device, held until the process ends; located when a context is
+ * created on the device), so the call allocates nothing and calls no hipMalloc, hipFree or
+ * hipMemset.  Limits: N <= KSG_NOALLOC_MAX_N, d_x + d_y + d_z <= 16.  Data holding NaN or
+ * infinity give a NaN estimate (no status: that would need a synchronisation).  Every call on
+ * one device shares that array: calls that overlap on one GPU (several streams or threads)
+ * race and must be ordered by the caller.  The search is the brute-force kernel of the batched
+ * path, so the estimate equals cmi_ksg's up to the order of the FP64 sum.
+ * Errors (host-side checks only): KSG_EINVAL (null pointers, dims, k, N above the limit),
+ * KSG_ETOOFEW, KSG_EDEVICE (the array could not be set up on this device, or a launch failed). */
+#define KSG_NOALLOC_MAX_N 65536
+int cmi_ksg_noalloc(ksg_ctx* ctx, const float* x, const float* y, const float* z, int64_t N,
+                    const int32_t dims[3], int32_t k, double* out_nats);
+
+/* ---------------------------------------------------------------------------
  * Batched estimates: every problem of the batch runs in one persistent launch
  * (work items = (problem, 256-query tile), longest first).
  *

@@ -9,6 +9,7 @@ fails loudly when it is missing.
 from ._binding import (  # noqa: F401
     KSG_MAX_DIMS,
     KSG_MAX_K,
+    KSG_NOALLOC_MAX_N,
     MLP_NFEAT,
     MLP_NPARAMS,
     Context,

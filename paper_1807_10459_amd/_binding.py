@@ -13,6 +13,7 @@ lib_path = os.path.join(_HERE, "libksgcmi.so")
 
 KSG_MAX_DIMS = 32
 KSG_MAX_K = 16
+KSG_NOALLOC_MAX_N = 65536
 MLP_NPARAMS = 5378
 MLP_NFEAT = 16
 
@@ -94,6 +95,7 @@ def _load():
         "ksg_take_timing": ([vp, C.POINTER(d), C.POINTER(i64), C.POINTER(d)], i32),
         "cmi_ksg": ([vp, vp, vp, vp, i64, vp, i32, C.POINTER(d)], i32),
         "cmi_ksg_batch": ([vp, C.POINTER(_Problem), i32, vp], i32),
+        "cmi_ksg_noalloc": ([vp, vp, vp, vp, i64, vp, i32, vp], i32),
         "ksg_maxstat": ([vp, vp, i32, i32, d, C.POINTER(_MaxStat)], i32),
         "ksg_embed": ([vp, vp, i32, i64, i32, i32, i32, vp, vp], i32),
         "ksg_greedy_step": ([vp, vp, vp, i64, vp, i32, vp, i32, vp, i32, i32, d, vp, C.POINTER(_MaxStat)], i32),
@@ -320,6 +322,18 @@ class Context:
         out = C.c_double()
         self._check(lib.cmi_ksg(self._h, p.x, p.y, p.z, p.n, dims, int(k), C.byref(out)), "cmi_ksg")
         return out.value
+
+    def cmi_noalloc(self, x, y, z=None, k: int = 4, out=None):
+        """cmi_ksg_noalloc: the estimate into the device FP64 tensor out[0] (a new one-element
+        tensor when out is None), queued on the stream without allocating in the library."""
+        import torch
+        p = Problem(x, y, z, k)._c()
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=x.device)
+        _check_dtype(out, torch.float64, "out")
+        dims = (C.c_int32 * 3)(p.dx, p.dy, p.dz)
+        self._check(lib.cmi_ksg_noalloc(self._h, p.x, p.y, p.z, p.n, dims, int(k), _ptr(out)), "cmi_ksg_noalloc")
+        return out
 
     def cmi_batch(self, problems: Sequence[Problem], out=None):
         import torch

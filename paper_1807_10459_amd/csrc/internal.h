@@ -170,5 +170,7 @@ hipError_t launch_embed(const float* data, int n_vars, int64_t T, int n_trials, 
                         hipStream_t stream);
 hipError_t launch_maxstat(const double* cmi, int c, int n_perm, double alpha, MaxStatOut* out,
                           hipStream_t stream);
+// Set-up of cmi_ksg_noalloc's static scratch array on the current device (once per device).
+hipError_t noalloc_init(int device);
 
 }  // namespace ksg

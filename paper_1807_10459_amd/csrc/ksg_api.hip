@@ -213,6 +213,9 @@ extern "C" int ksg_ctx_create(ksg_ctx** out, int device, void* hip_stream) {
     return KSG_ENOMEM;
   }
   c->d_flag = c->d_counter + 1;
+  // cmi_ksg_noalloc's static array on this device: located once; a failure only disables that
+  // entry point (it reports KSG_EDEVICE)
+  (void)noalloc_init(device);
   *out = c;
   return KSG_OK;
 }
