@@ -567,8 +567,6 @@ def main():
     ap.add_argument("--dataset", default=None, help="c4: load the training set from this npz")
     ap.add_argument("--dump-dataset", default=None,
                     help="build the learned-null training set and save it (npz) instead of benchmarking")
-    ap.add_argument("--valu-probe", action="store_true",
-                    help="print the measured issue rate of each VALU instruction class and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (a known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -581,18 +579,6 @@ def main():
     import torch
     import paper_1807_10459_amd as ksg
     import workloads
-
-    if args.valu_probe:  # issue rates of the VALU instruction classes (roofline calibration)
-        ctx = ksg.Context(0)
-        names = ["v_sub_f32", "v_max3_f32 |.|", "v_cmp_lt_f32 + v_addc (2 instr)", "v_med3_f32",
-                 "v_fma_f32", "v_max_f32", "v_max_f32 |.| (VOP3)", "v_min_u32", "v_cndmask_b32",
-                 "v_add_u32", "v_cmp_lt_f32 -> SGPR pair", "v_and_b32", "v_sub_f32 SGPR operand",
-                 "v_min3_f32", "v_sub_u32", "v_lshrrev_b32", "v_add3_u32", "v_mov_b32 from SGPR"]
-        rates = {f"{i} {n}": round(ctx.valu_probe(i) / 1e12, 2) for i, n in enumerate(names)}
-        lds = ctx.lds_probe()
-        print(json.dumps({"valu_probe_T_lane_ops_per_s": rates, "lds_read_TB_per_s": round(lds / 1e12, 2),
-                          "lds_read_bytes_per_clk_per_cu": round(lds / (ksg.device_props(0)["cus"] * 2.4e9), 1)}))
-        return
 
     if args.workload == "c4":
         ctx = ksg.Context(0)

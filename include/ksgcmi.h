@@ -116,9 +116,14 @@ typedef enum ksg_option {
   KSG_OPT_GROUP_SIZE = 2,   /* problems searched together when they share Y, Z, N and k and
                                have 1-D X: -1 (default) = autotuned per conditioning dimension,
                                0 = off, 8 or 16 = forced */
-  KSG_OPT_USE_GRAPH = 3,    /* accepted, no effect: steps are launched directly on the stream (a
-                             * greedy step is 6-8 launches around kernels of milliseconds, so
-                             * launch overhead is below 0.1%); no hipGraph is captured */
+  KSG_OPT_USE_GRAPH = 3,    /* 1: capture the launches of a batch into a HIP graph (with private
+                             * copies of its descriptors) and replay the graph when the same batch
+                             * (same problems, columns, gathers, output and options) comes again,
+                             * skipping the host planning, the upload and the per-launch overhead;
+                             * at most 32 graphs per context (least recently used dropped), retired
+                             * when a work buffer grows.  Used only with KSG_OPT_TIMING = 0 and
+                             * KSG_OPT_CHECK_FINITE = 0 (select_parents checks its data once and
+                             * runs its steps without the check).  0 (default): direct launches */
   KSG_OPT_TIMING = 4,       /* 1: time every search-kernel launch with HIP events (default 0) */
   KSG_OPT_ALGORITHM = 5,    /* KSG algorithm of every later estimate (default 1):
                              * 1: eps_i = joint k-th neighbour distance, strict counts in XZ, YZ, Z,
@@ -131,6 +136,10 @@ typedef enum ksg_option {
                              *    counts_out then holds these counts (n_z = N-1 without Z), eps_out
                              *    the k-th neighbour's joint distance, local_out the pointwise values.
                              *    Problems are searched one by one (no grouping). */
+  KSG_OPT_GROUP_CHUNK = 7,  /* grouped problems run in chunks whose radii (FP32) and Y/Z terms
+                             * (FP64) hold at most this many elements: 0 (default) = 2^27, i.e.
+                             * 1.5 GiB of workspace; smaller values bound the workspace (more
+                             * launches, same results) */
   KSG_OPT_WINDOWS = 6       /* 1 (default): single problems (not grouped) with k <= 4, N >= 2048,
                              * no per-point outputs and an unpermuted Z column are searched with
                              * their rows in the order of that column, each tile scanning only the
@@ -141,6 +150,10 @@ typedef enum ksg_option {
 } ksg_option;
 int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
 
+/* KSG_OPT_USE_GRAPH bookkeeping (host int64 outputs): batches captured into graphs, graph
+ * replays, and graphs held now.  Errors: KSG_EINVAL. */
+int ksg_graph_stats(ksg_ctx* ctx, int64_t* captures, int64_t* replays, int64_t* held);
+
 /* Autotuner of the grouped search kernel: for k <= 4 and k <= 8 and every conditioning
  * dimension m = 0..14, time the group sizes 8 and 16 on a synthetic batch (32 problems of n
  * points sharing Y and Z) and keep the faster for KSG_OPT_GROUP_SIZE = -1.  cache_path (host
@@ -149,22 +162,6 @@ int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
  * tuned_out (host int32 [30] or NULL): the chosen sizes, k <= 4 first.  Synchronises.
  * Errors: KSG_EINVAL (n outside [256, 2^20]), KSG_ENOMEM, KSG_EDEVICE. */
 int ksg_autotune(ksg_ctx* ctx, int64_t n, const char* cache_path, int32_t* tuned_out);
-
-/* Roofline calibration: instructions per second x 64 lanes ("lane operations") of one VALU
- * instruction class on the context's device, from 16 independent chains per lane with no
- * memory traffic: kind 0 v_sub_f32, 1 v_max3_f32 (|.| operands), 2 v_cmp_lt_f32 + v_addc
- * (a compare-and-count, two instructions), 3 v_med3_f32, 4 v_fma_f32, 5 v_max_f32, 6
- * v_max_f32 with |.| (VOP3), 7 v_min_u32, 8 v_cndmask_b32, 9 v_add_u32, 10 v_cmp_lt_f32 into an
- * SGPR pair, 11 v_and_b32, 12 v_sub_f32 with an SGPR operand, 13 v_min3_f32, 14 v_sub_u32,
- * 15 v_lshrrev_b32, 16 v_add3_u32, 17 v_mov_b32 from an SGPR.  Synchronises.
- * Errors: KSG_EINVAL, KSG_EDEVICE. */
-int ksg_valu_probe(ksg_ctx* ctx, int32_t kind, int32_t iters, double* lane_ops_per_s);
-
-/* LDS read bandwidth of the context's device in bytes per second: 8 work-groups of 256 lanes
- * per CU, each lane reading 8 independent 16-byte values per iteration from a 64 KB LDS
- * array without bank conflicts, iters iterations.  Synchronises.  Output is a host pointer.
- * Errors: KSG_EINVAL, KSG_EDEVICE. */
-int ksg_lds_probe(ksg_ctx* ctx, int32_t iters, double* bytes_per_s);
 
 /* With KSG_OPT_TIMING on: device time of the search kernels (radius, counts and per-tile
  * digamma sums, finalisation excluded) summed over all search phases since the last call, in
@@ -224,8 +221,16 @@ int cmi_ksg_noalloc(ksg_ctx* ctx, const float* x, const float* y, const float* z
                     const int32_t dims[3], int32_t k, double* out_nats);
 
 /* ---------------------------------------------------------------------------
- * Batched estimates: every problem of the batch runs in one persistent launch
- * (work items = (problem, 256-query tile), longest first).
+ * Batched estimates: all problems of the batch are searched by one set of launches on the
+ * context's stream, one work-group per work item (a 256-query tile of a problem or of a group
+ * of problems), longest work first, so that the hardware dispatcher hands the work out as
+ * compute units free up.  The set: the column pack (with the surrogate gathers); for problems
+ * that share Y and Z and have 1-D X (the candidates x surrogates of a greedy step) the key
+ * order, block interleave and three search launches per chunk of groups (radius, Y/Z counts,
+ * X counts with the digamma partial sums); for the other problems one launch per column
+ * count or shape (brute force or key-ordered windows), run side by side on three auxiliary
+ * streams joined back by events; then one finalisation launch.  With KSG_OPT_USE_GRAPH the
+ * set is captured once into a HIP graph and replayed when the same batch comes again.
  *
  * perm_x: NULL, or an int32 row gather of length n applied to X only
  * (X'[i] = X[perm_x[i]]: a permutation surrogate, Summary network-inference
@@ -464,8 +469,10 @@ int ksg_mlp_set_norm(ksg_mlp* m, const float* mu, const float* sd);
 /* Copy FP32 master parameters to host [5378] (bf16 = 1: the BF16-rounded values in use). */
 int ksg_mlp_get_params(const ksg_mlp* m, float* out, int32_t bf16);
 int ksg_mlp_set_params(ksg_mlp* m, const float* params);
-/* Forward: feats device FP32 [B][16] raw features -> out device FP32 [B][2]. */
+/* Forward: feats device FP32 [B][16] raw features -> out device FP32 [B][2].  ksg_mlp_predict is
+ * the same call under the name of the survey's boundary. */
 int ksg_mlp_forward(ksg_ctx* ctx, const ksg_mlp* m, const float* feats, int64_t B, float* out);
+int ksg_mlp_predict(ksg_ctx* ctx, const ksg_mlp* m, const float* feats, int64_t B, float* out);
 /* Loss and gradient of L = (1/B) sum_b 0.5 |out_b - t_b|^2 with respect to the
  * BF16 parameters: grad device FP32 [5378], loss device FP32 [1]. */
 int ksg_mlp_grad(ksg_ctx* ctx, const ksg_mlp* m, const float* feats, const float* targets,

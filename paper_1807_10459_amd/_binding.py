@@ -88,9 +88,8 @@ def _load():
         "ksg_last_error": ([vp], C.c_char_p),
         "ksg_ctx_set_option": ([vp, i32, i64], i32),
         "ksg_autotune": ([vp, i64, C.c_char_p, vp], i32),
-        "ksg_valu_probe": ([vp, i32, i32, C.POINTER(d)], i32),
-        "ksg_lds_probe": ([vp, i32, C.POINTER(d)], i32),
         "ksg_last_work": ([vp, vp], i32),
+        "ksg_graph_stats": ([vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)], i32),
         "ksg_last_kernels": ([vp, vp, vp, vp], i32),
         "ksg_take_timing": ([vp, C.POINTER(d), C.POINTER(i64), C.POINTER(d)], i32),
         "cmi_ksg": ([vp, vp, vp, vp, i64, vp, i32, C.POINTER(d)], i32),
@@ -238,6 +237,7 @@ class Context:
     OPT_TIMING = 4
     OPT_ALGORITHM = 5
     OPT_WINDOWS = 6
+    OPT_GROUP_CHUNK = 7
 
     def __init__(self, device: int = 0, stream=None):
         import torch
@@ -281,17 +281,11 @@ class Context:
                                      out.ctypes.data), "ksg_autotune")
         return {"k<=4": out[:15].tolist(), "k<=8": out[15:].tolist()}
 
-    def valu_probe(self, kind: int, iters: int = 4096) -> float:
-        """Lane operations per second of one VALU instruction class (see ksg_valu_probe)."""
-        r = C.c_double()
-        self._check(lib.ksg_valu_probe(self._h, int(kind), int(iters), C.byref(r)), "ksg_valu_probe")
-        return r.value
-
-    def lds_probe(self, iters: int = 4096) -> float:
-        """LDS read bytes per second of the device (see ksg_lds_probe)."""
-        r = C.c_double()
-        self._check(lib.ksg_lds_probe(self._h, int(iters), C.byref(r)), "ksg_lds_probe")
-        return r.value
+    def graph_stats(self) -> dict:
+        """Batches captured into graphs, graph replays and graphs held (KSG_OPT_USE_GRAPH)."""
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(lib.ksg_graph_stats(self._h, C.byref(a), C.byref(b), C.byref(c)), "ksg_graph_stats")
+        return dict(captures=a.value, replays=b.value, held=c.value)
 
     def take_timing(self):
         """(search-kernel milliseconds, launches, algorithmic FP32 ops) since the last call."""

@@ -28,11 +28,11 @@ SOURCES = [  # longest compiles first, so that the parallel build ends early
     "ksg_yzcount.hip",
     "ksg_misc.hip",
     "ksg_api.hip",
+    "batch.hip",
     "ksg_noalloc.hip",
     "greedy.hip",
     "mlp_kernels.hip",
     "mlp_api.hip",
-    "valu_probe.hip",
     "autotune.hip",
 ]
 

@@ -135,6 +135,10 @@ extern "C" int ksg_mlp_forward(ksg_ctx* c, const ksg_mlp* m, const float* feats,
   return KSG_OK;
 }
 
+extern "C" int ksg_mlp_predict(ksg_ctx* c, const ksg_mlp* m, const float* feats, int64_t B, float* out) {
+  return ksg_mlp_forward(c, m, feats, B, out);
+}
+
 static int ensure_partials(ksg_ctx* c, ksg_mlp* m, int64_t B) {
   const int nb = (int)((B + kGradRows - 1) / kGradRows);
   if (nb <= m->partial_blocks) return KSG_OK;

@@ -33,6 +33,63 @@ struct Problem {
   int out_index;
 };
 
+// The host plan of one batch (batch.hip): descriptors, work items, pack jobs and the launch
+// layout, in the order the upload writes them.
+struct BatchPlan {
+  struct Segment {
+    int D, kp, off, count;
+    double cost;  // brute-force operations of its problems (launch scheduling)
+  };
+  struct Chunk {
+    std::array<int, 3> cls;       // m, G, KP
+    std::vector<WorkItem> items;  // radius and X count launches (same items)
+    size_t item_off = 0;
+    size_t ydesc_off = 0, n_ydesc = 0;
+    size_t yitem_off = 0, n_yitems = 0;
+  };
+  int np = 0;
+  std::vector<ProbDesc> descs;
+  std::vector<GroupDesc> gdescs;
+  std::vector<YZDesc> ydescs;
+  std::vector<WorkItem> items;   // ungrouped items: brute force (or algorithm-2 segments), windows, wide
+  std::vector<WorkItem> yitems;  // Y/Z count items of every chunk
+  std::vector<Chunk> chunks;
+  std::vector<PackJob> jobs;     // pool columns (destinations resolved)
+  std::vector<PackJob> inplace;  // in-place columns, for the finite check
+  std::vector<Segment> segments, wsegments;
+  Segment wide_seg{0, 5, 0, 0, 0.0};
+  std::vector<std::pair<const float*, int64_t>> wsets;  // window sets: (key column, N)
+  std::vector<int64_t> wsigma_off;                      // their key orders in the pool
+  int n_plain_items = 0;
+  double plain_cost = 0.0;
+  int common_shape = -2;
+  int kp = 5;
+  int max_pad = 0;
+  int parts = 0;
+  int64_t chunk_elems_max = 0;
+  size_t n_gitems = 0;
+  float* pool_base = nullptr;
+  double brute_ops = 0.0;
+  int64_t n_groups = 0;
+  size_t desc_bytes() const;
+  size_t item_count() const;
+};
+
+// A captured batch: the instantiated graph, the key it was captured for and its private copies
+// of the descriptors, work items and pack jobs.
+struct GraphEntry {
+  std::vector<uint64_t> key;
+  uint64_t hash = 0;
+  uint64_t gen = 0;  // buffer generation at capture
+  uint64_t last_use = 0;
+  hipGraphExec_t exec = nullptr;
+  DevBuf desc, items, jobs;
+  int64_t n_items = 0, n_groups = 0;
+};
+
+// Grouped launches run in chunks of at most this many E / T elements (KSG_OPT_GROUP_CHUNK).
+constexpr int64_t kGroupChunkElems = int64_t(1) << 27;
+
 }  // namespace ksg
 
 void ksg_build_harmonic(int64_t nmax, double* out);
@@ -57,7 +114,8 @@ struct ksg_ctx {
   int algorithm = 1;             // KSG algorithm of every estimate: 1 or 2
   bool use_windows = true;       // key-ordered window search for eligible single problems
   int tuned_g[2][15] = {{0}};    // [k <= 4 ? 0 : 1][m]: group size picked by the autotuner (0 = default)
-  bool use_graph = true;         // KSG_OPT_USE_GRAPH: recorded only (no graph capture)
+  bool use_graph = false;        // KSG_OPT_USE_GRAPH: capture batches into HIP graphs and replay them
+  int64_t group_chunk_elems = 0; // KSG_OPT_GROUP_CHUNK: 0 = kGroupChunkElems
 
   ksg::DevBuf htab, pool, desc, items, partials, jobs, tmp, embed, cmi, aux, feat;
   ksg::DevBuf ebuf, tbuf;  // grouped search: radii E (FP32) and Y/Z count terms T (FP64)
@@ -115,6 +173,22 @@ struct ksg_ctx {
   int ensure_htab(int64_t n);
   int validate(const ksg::Problem& p, int index);
   int run_batch(const std::vector<ksg::Problem>& probs, double* d_out);
+  int plan_batch(const std::vector<ksg::Problem>& probs, ksg::BatchPlan& plan);
+  int upload_batch(const ksg::BatchPlan& plan, void* d_desc, void* d_items, void* d_jobs);
+  int enqueue_batch(const ksg::BatchPlan& plan, const void* d_desc, const ksg::WorkItem* d_items,
+                    const ksg::PackJob* d_jobs, double* d_out);
+
+  // KSG_OPT_USE_GRAPH: captured batches (least recently used evicted beyond kMaxGraphs).  buf_gen
+  // counts reallocations of the work buffers a graph writes (pool, E, T, partials, harmonic
+  // table); a graph captured at an older generation is not replayed.
+  static constexpr size_t kMaxGraphs = 32;
+  std::vector<ksg::GraphEntry> graphs;
+  uint64_t buf_gen = 0, graph_clock = 0;
+  int64_t graph_captures = 0, graph_replays = 0;
+  hipStream_t capture_stream = nullptr;
+  int run_batch_graph(const std::vector<ksg::Problem>& probs, double* d_out);
+  void drop_graph(ksg::GraphEntry& g);
+  void clear_graphs();
   int check_columns_finite(const std::vector<ksg::PackJob>& cols, int max_pad);
   int maxstat_async(const double* d_cmi, int cands, int P, double alpha, int slot);
 };

@@ -384,27 +384,6 @@ def test_autotune_table_and_cache(lib, ctx, tmp_path):
     assert open(path).read().count("\n") == 1
 
 
-def test_valu_probe_classes(lib, ctx):
-    """Every instruction class of the roofline calibration runs and reports a rate below the
-    part's 2 x 16-lane issue ceiling (256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz = 78.6 T)."""
-    for kind in range(18):
-        r = ctx.valu_probe(kind, iters=256)
-        assert 1e12 < r < 1.05 * 78.65e12, (kind, r)
-    with pytest.raises(lib.KsgError):
-        ctx.valu_probe(18)
-
-
-def test_lds_probe(lib, ctx):
-    """The LDS read bandwidth probe runs and reports between 32 and 512 bytes per clock per CU
-    at the 2.4 GHz engine clock (the part's LDS serves 128 bytes per clock or more)."""
-    r = ctx.lds_probe(iters=512)
-    per_clk = r / (lib.device_props(0)["cus"] * 2.4e9)
-    print("LDS bytes/clk/CU", per_clk)
-    assert 32 < per_clk < 512, per_clk
-    with pytest.raises(lib.KsgError):
-        ctx.lds_probe(0)
-
-
 def test_device_props(lib):
     """The runtime's figures for the device the roofline is priced on."""
     import torch
