@@ -76,7 +76,7 @@ def cpu_baseline(cand, y, perms, order, sample_per_m=2, workers=None, alg=1):
             x = cand[pool[ci]] if p == 0 else cand[pool[ci]][perms[p - 1]]
             tasks.append((x, y, z, K, alg))
             keys.append((m, ci, p))
-    workers = workers or min(8, os.cpu_count() or 1)
+    workers = workers or (os.cpu_count() or 1)
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(workers) as pool_:
         res = pool_.map(_cpu_task, tasks)
@@ -423,6 +423,30 @@ KERNEL_NAMES = {"radius": "ksg_group_radius_kernel (k-NN radius of each problem 
                                "distance, rectangle sides, <= counts; operations counted over the pairs visited)"}
 
 
+def _host_cpu():
+    """lscpu's model, sockets, physical cores and hardware threads of the host (Linux)."""
+    import subprocess
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ":" in ln:
+                key, val = ln.split(":", 1)
+                info[key.strip()] = val.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+
+    def num(key):
+        try:
+            return int(info.get(key, ""))
+        except ValueError:
+            return None
+    sockets, cores_per, threads = num("Socket(s)"), num("Core(s) per socket"), num("CPU(s)")
+    return {"model": info.get("Model name", _cpu_model()), "sockets": sockets,
+            "physical_cores": sockets * cores_per if sockets and cores_per else None,
+            "hardware_threads": threads, "threads_usable": os.cpu_count()}
+
+
 def _cpu_model():
     """The host CPU's model name (Linux), for the CPU baseline's record."""
     try:
@@ -567,6 +591,8 @@ def main():
     ap.add_argument("--dataset", default=None, help="c4: load the training set from this npz")
     ap.add_argument("--dump-dataset", default=None,
                     help="build the learned-null training set and save it (npz) instead of benchmarking")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the pass that replays the steps from HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device-to-device copy (a known-size kernel for HBM counters)")
     args = ap.parse_args()
@@ -662,54 +688,85 @@ def main():
             results[m] = r
         return cand, y, results
 
+    # The inputs are checked for non-finite values and permutation range once, before timing
+    # (as select_parents does); the timed steps trust them.
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    ctx.set_option(ctx.OPT_TIMING, 1)
-    ctx.take_timing()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        cand, y, results = step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    k_ms, k_launches, k_ops = ctx.take_timing()
-    kern = ctx.last_kernels()
-    ctx.set_option(ctx.OPT_TIMING, 0)
+    ctx.set_option(ctx.OPT_CHECK_FINITE, 0)
+    step()
+
+    def timed(use_graph, timing):
+        ctx.set_option(ctx.OPT_USE_GRAPH, int(use_graph))
+        if use_graph:
+            step()  # capture
+        ctx.set_option(ctx.OPT_TIMING, int(timing))
+        ctx.take_timing()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        k = ctx.take_timing()
+        kern = ctx.last_kernels()
+        ctx.set_option(ctx.OPT_TIMING, 0)
+        ctx.set_option(ctx.OPT_USE_GRAPH, 0)
+        return wall, k, kern, res
+
+    # (1) direct launches, every search launch timed by its own HIP events on its stream
+    wall, (k_ms, k_launches, k_ops), kern, (cand, y, results) = timed(False, True)
+    # (2) the same steps replayed from HIP graphs (one graph per greedy step)
+    g_wall, _, _, _ = timed(True, False) if args.algorithm == 1 and not args.no_graph else (None, None, None, None)
+    graph_stats = ctx.graph_stats()
+    head_wall = min(wall, g_wall) if g_wall else wall
 
     n_cmi = sum((25 - m) * (N_PERM + 1) for m in FORCED_M)
-    ms_step = 1000.0 * wall / args.steps
-    value = n_cmi * args.steps / wall
+    value = n_cmi * args.steps / head_wall
     kernels = {}
     for name, (ms, ops, nl) in kern.items():
         if nl:
             kernels[name] = {"ms_per_launch": round(ms / nl, 3), "launches": nl,
-                             "ops_per_launch": ops / nl, "achieved": round(ops / (ms * 1e-3) / 1e12, 3),
-                             "frac": round(ops / (ms * 1e-3) / PEAK_VALU, 4)}
+                             "executed_ops_per_launch": ops / nl,
+                             "executed_ops_rate": round(ops / (ms * 1e-3) / 1e12, 3)}
     dom = max(kernels, key=lambda kname: kern[kname][0])
     d_ms, d_ops, d_n = kern[dom]
-    achieved = d_ops / (d_ms * 1e-3)
+    t_launch = d_ms / d_n * 1e-3
+    # Algorithmic operations of the method (brute force over ordered pairs, SURVEY 8(d) counts):
+    # radius 2D per pair, counts 2D + 2 per pair, for every problem of the step.
+    pairs = N * (N - 1)
+    brute_radius = sum((25 - m) * (N_PERM + 1) * pairs * 2 * (m + 2) for m in FORCED_M) * args.steps
+    brute_counts = sum((25 - m) * (N_PERM + 1) * pairs * (2 * (m + 2) + 2) for m in FORCED_M) * args.steps
+    brute_of = {"radius": brute_radius, "x_count": brute_counts, "yz_count": brute_counts,
+                "single": brute_radius + brute_counts}
+    for name, rec in kernels.items():
+        ms_total = kern[name][0]
+        rec["effective_ops_rate"] = round(brute_of.get(name, 0.0) / (ms_total * 1e-3) / 1e12, 3)
+        vi = _counter_record("valu_wave_instructions_per_launch", name)
+        if vi is not None:
+            rec["valu_lane_instr_rate"] = round(vi * 64 / (ms_total / kern[name][2] * 1e-3) / 1e12, 3)
+            rec["frac"] = round(vi * 64 / (ms_total / kern[name][2] * 1e-3) / PEAK_VALU, 4)
+    valu_instr = _counter_record("valu_wave_instructions_per_launch", dom)
+    achieved = None if valu_instr is None else valu_instr * 64 / t_launch
     roofline = {
         "bound": "alu",
-        "achieved": round(achieved / 1e12, 3),
+        "achieved": None if achieved is None else round(achieved / 1e12, 3),
         "peak": round(PEAK_VALU / 1e12, 3),
-        "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_VALU, 4),
-        "frac_4cycle_class": round(achieved / PEAK_VALU_4CYCLE, 4),
+        "unit": "T VALU lane-instructions/s",
+        "frac": None if achieved is None else round(achieved / PEAK_VALU, 4),
         "traffic": _traffic_record(dom),
-        # executed VALU lane-instructions (SQ_INSTS_VALU x 64, committed counter record) over
-        # 39.3 T lane-instructions/s (one instruction per 4 cycles per SIMD) x this run's time
-        "valu_issue_frac_4cycle": (None if _counter_record("valu_wave_instructions_per_launch", dom) is None
-                                   else round(_counter_record("valu_wave_instructions_per_launch", dom) * 64
-                                              / (PEAK_VALU_4CYCLE * d_ms / d_n * 1e-3), 3)),
         "kernel": KERNEL_NAMES[("alg2" if args.no_windows else "window_alg2") if args.algorithm == 2 else
                                ("window" if dom == "single" and not args.no_windows else dom)],
         "kernel_ms_per_launch": round(d_ms / d_n, 3),
         "launches": d_n,
-        "ops_per_launch": d_ops / d_n,
+        "valu_wave_instructions_per_launch": valu_instr,
+        "how": "achieved = SQ_INSTS_VALU per launch (committed rocprofv3 counter record) x 64 lanes / this "
+               "run's mean launch time (HIP events); peak = 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz",
+        # the method's brute-force operation count for the launch's problems over its time: above the
+        # peak because the key windows, exact skips and shared Y/Z distances do not execute most of it
+        "effective_ops_rate": kernels[dom]["effective_ops_rate"],
+        "algorithmic_ops_per_launch": brute_of.get(dom, 0.0) / d_n,
     }
-    search = {"ms_per_step": round(k_ms / args.steps, 3), "kernels": kernels,
-              "achieved_all_kernels": round(k_ops / (k_ms * 1e-3) / 1e12, 3)}
+    search = {"ms_per_step": round(k_ms / args.steps, 3), "kernels": kernels}
 
     line = {
         "metric": "CMI estimates/sec incl. surrogates (N=10k, k=4)",
@@ -718,7 +775,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 2),
+        "ms_per_step": round(1000.0 * head_wall / args.steps, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -729,10 +786,13 @@ def main():
                                "k=4, 200 surrogates, conditioning dims m=1..8 (forced path), "
                                f"{n_cmi} CMIs per step" + (", KSG algorithm 2" if args.algorithm == 2 else ""),
                    "n_cmi_per_step": n_cmi},
+        "launch_modes": {"direct_ms_per_step": round(1000.0 * wall / args.steps, 2),
+                         "graph_ms_per_step": None if g_wall is None else round(1000.0 * g_wall / args.steps, 2),
+                         "headline": "graph" if g_wall and g_wall < wall else "direct",
+                         "graph_captures": graph_stats["captures"], "graph_replays": graph_stats["replays"]},
         "roofline": roofline,
         "search": search,
-        "autotune": {"group_size_k4_by_m": tuned["k<=4"] if tuned else None,
-                     "seconds": round(t_tune, 3)},
+        "autotune": {"choices": tuned, "seconds": round(t_tune, 3)} if tuned else None,
         "device": {k_: v_ for k_, v_ in ksg.device_props(0).items()
                    if k_ in ("name", "arch", "cus", "clock_khz", "mem_clock_khz", "mem_bus_bits",
                              "total_mem", "l2_bytes", "lds_per_cu")},
@@ -750,20 +810,23 @@ def main():
     if not args.no_cpu_baseline:
         cand_np = cand.cpu().numpy()
         y_np = y.cpu().numpy()
-        cps, cores, desc, vals = cpu_baseline(cand_np, y_np, perms_np, order, alg=args.algorithm)
+        workers = os.cpu_count() or 1
+        per_m = max(2, -(-workers // 8))  # at least one task per worker
+        cps, cores, desc, vals = cpu_baseline(cand_np, y_np, perms_np, order, sample_per_m=per_m,
+                                              workers=workers, alg=args.algorithm)
         # The sampled oracle values double as a parity spot check of the timed run.
         worst = 0.0
         for (m, ci, p), v in vals.items():
             g = float(tables[m][ci, p].cpu())
             worst = max(worst, abs(g - v) / max(1.0, abs(v)))
         line["cpu_baseline"] = {"value": round(cps, 3), "unit": "CMI/s", "cores": cores, "kind": "oracle",
-                                "cpu_model": _cpu_model(), "sample": desc}
+                                "cpu_model": _cpu_model(), "host": _host_cpu(), "sample": desc}
         line["parity_spot_check_max_rel_err"] = worst
         kps, threads = kdtree_context(cand_np, y_np, perms_np, order)
         line["cpu_context"] = {"value": round(kps, 3), "unit": "CMI/s", "threads": threads,
                                "kind": "SciPy cKDTree KSG in FP64 (context only: a tree search, not the "
                                        "oracle and not FP32-exact)",
-                               "sample": "the same 16 CMIs as cpu_baseline"}
+                               "sample": "16 of the step's CMIs (2 per m)"}
     line["steps_detail"] = {str(m): {"c_star_candidate": [c for c in range(25) if c not in order[:m]][r["c_star"]],
                                      "t_obs": round(r["t_obs"], 6), "pval": r["pval"]}
                             for m, r in results.items()}
