@@ -247,19 +247,21 @@ def c4_evaluate(ctx, args, log):
     perms = torch.from_numpy(workloads.permutations(N, 500, seed=33)).cuda()
     targets = [int(t) for t in args.targets.split(",")] if args.targets else list(range(20))
     res = {}
-    for mode in ("plain", "learned"):
+    # plain: the permutation test on every step, no network; learned: the gate first, the
+    # surrogates only for borderline steps; judged (--judge): the gate and the plain test on every
+    # step, the plain decision taken (per-step agreement of the gate, not timed against)
+    modes = ("plain", "learned") + (("judged",) if args.judge else ())
+    for mode in modes:
         torch.cuda.synchronize()
         tm = time.perf_counter()
         out = {}
         for t in targets:
             kw = dict(k=K, max_lag=MAX_LAG, alpha=0.05, omnibus=True)
-            if mode == "learned":
-                kw.update(learned=net, margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"])
-            else:  # the plain run also evaluates the gate on every step, for step agreement
-                kw.update(learned=net, margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"], judge=True)
+            if mode != "plain":
+                kw.update(learned=net, margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"], judge=mode == "judged")
             out[t] = ctx.select_parents(data, t, perms, **kw)
             log(f"{mode} target {t}: parents {out[t]['parents']} steps {out[t]['n_steps']} "
-                f"fallback {out[t]['n_fallback']} disagree {out[t]['n_disagree']} "
+                f"truncated {out[t]['truncated']} fallback {out[t]['n_fallback']} disagree {out[t]['n_disagree']} "
                 f"{time.perf_counter() - tm:.1f} s")
         torch.cuda.synchronize()
         res[mode] = (out, time.perf_counter() - tm)
@@ -277,8 +279,22 @@ def c4_evaluate(ctx, args, log):
     exact = sum(1 for t in targets if plain[t]["parents"] == learned[t]["parents"])
     n_par_plain = sum(len(r["parents"]) for r in plain.values())
     n_par_learned = sum(len(r["parents"]) for r in learned.values())
-    steps_judged = sum(r["n_steps"] for r in plain.values())
-    disagree = sum(r["n_disagree"] for r in plain.values())
+    # per-step agreement without a judge run: along each target's common path (steps whose
+    # conditioning sets agree), the learned run's decision (the gate's, or the surrogates' on a
+    # borderline step) against the plain run's
+    steps_compared, steps_agree = 0, 0
+    for t in targets:
+        pp, ll = plain[t], learned[t]
+        for i in range(min(len(pp["steps"]), len(ll["steps"]))):
+            if pp["candidates"][:i] != ll["candidates"][:i]:
+                break
+            st_l = ll["steps"][i]
+            dec_l = (st_l["verdict"] > 0) if st_l["verdict"] in (-1, 1) else (st_l["plain"] == 1)
+            steps_compared += 1
+            steps_agree += int(dec_l == (pp["steps"][i]["plain"] == 1))
+    if "judged" in res:
+        steps_judged = sum(r["n_steps"] for r in res["judged"][0].values())
+        disagree = sum(r["n_disagree"] for r in res["judged"][0].values())
     true_edges = {(s_, t_) for (s_, t_, _) in net3.edges}
     # ablation: the same gate driven by a per-(N, c) bucket mean-threshold table, evaluated on
     # the plain run's judged steps (pool size c = 100 - step in the multivariate-TE pool)
@@ -287,7 +303,7 @@ def c4_evaluate(ctx, args, log):
     ablation = bucket_table_ablation(feats[tr].cpu().numpy(), targ[tr].cpu().numpy(),
                                      feats[hi_idx].cpu().numpy(), obs[hi_idx].cpu().numpy(), 0.0025, eval_steps)
     ablation["network_held_out_fallback"] = round(cal["fallback"], 4)
-    ablation["network_eval_steps_decided"] = sum(1 for r in plain.values() for st in r["steps"]
+    ablation["network_eval_steps_decided"] = sum(1 for r in learned.values() for st in r["steps"]
                                                  if st["verdict"] in (-1, 1))
     log(f"ablation: {ablation}")
     return {
@@ -301,8 +317,13 @@ def c4_evaluate(ctx, args, log):
         "learned_seconds": round(t_learned, 2),
         "pair_agreement": agree_pairs / (len(targets) * n_vars),
         "exact_parent_set_rate": exact / len(targets),
-        "step_agreement": 1.0 - disagree / max(steps_judged, 1),
-        "steps_judged": steps_judged,
+        "step_agreement_common_path": steps_agree / max(steps_compared, 1),
+        "steps_compared": steps_compared,
+        "judged_step_agreement": (1.0 - disagree / max(steps_judged, 1)) if "judged" in res else None,
+        "truncated_targets_plain": sum(int(r["truncated"]) for r in plain.values()),
+        "truncated_targets_learned": sum(int(r["truncated"]) for r in learned.values()),
+        "parents_plain": {str(t): r["parents"] for t, r in plain.items()},
+        "parents_learned": {str(t): r["parents"] for t, r in learned.items()},
         "learned_fallback_steps": sum(r["n_fallback"] for r in learned.values()),
         "learned_gate_steps": sum(r["n_gate_decided"] for r in learned.values()),
         "learned_cmi": sum(r["n_cmi"] for r in learned.values()),
@@ -589,6 +610,8 @@ def main():
                     help="ar2: CMI/s on the AR(2) forced path (default); c4: learned vs plain null")
     ap.add_argument("--targets", default=None, help="c4: comma-separated targets (default all 20)")
     ap.add_argument("--dataset", default=None, help="c4: load the training set from this npz")
+    ap.add_argument("--judge", action="store_true",
+                    help="c4: also run the judged selection (gate and plain test on every step)")
     ap.add_argument("--dump-dataset", default=None,
                     help="build the learned-null training set and save it (npz) instead of benchmarking")
     ap.add_argument("--no-graph", action="store_true",
