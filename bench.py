@@ -125,8 +125,8 @@ def kdtree_context(cand, y, perms, order, per_m=2):
 
 # (kind, seed, size): ar2 -> N; logistic -> trials of 3000 samples.  Seeds are disjoint from
 # the evaluation network (logistic seed 3).
-TRAIN_PLAN = ([("ar2", 1000 + i, n) for i, n in enumerate([2000] * 30 + [5000] * 16 + [10000] * 8)] +
-              [("logistic", 2000 + i, t) for i, t in enumerate([1] * 40 + [2] * 12 + [5] * 4 + [10] * 1)])
+AR2_PLAN = [("ar2", 1000 + i, n) for i, n in enumerate([2000] * 30 + [5000] * 16 + [10000] * 8)]
+TRAIN_PLAN = AR2_PLAN + [("logistic", 2000 + i, t) for i, t in enumerate([1] * 40 + [2] * 12 + [5] * 8 + [10] * 6)]
 
 
 def _subsets_for(g):
@@ -214,6 +214,67 @@ def bucket_table_ablation(F, Tg, HF, HO, rate, eval_steps):
     return {"margin_lo": round(lo, 4), "margin_hi": round(hi, 4), "buckets": len(means),
             "held_out_fallback": round(float(band.mean()), 4),
             "eval_steps_decided": decided, "eval_steps_fallback": fallback, "eval_steps_wrong": wrong}
+
+
+def selection_bench(ctx, log):
+    """Parents/s of the learned null against the plain permutation test on the AR(2) network
+    (N = 10,000, 25 candidates, k = 4, 200 surrogates), every node as target.  The threshold
+    network is trained in this run on the plain greedy paths of the 54 seeded AR(2) training
+    networks (seeds disjoint from the evaluation network), margins calibrated on the held-out
+    ones at 0.25 % wrong decisions; that one-time cost is reported apart from the timed runs."""
+    import torch
+    import workloads
+    from paper_1807_10459_amd.learned_null import calibrate, train_threshold_net
+    t0 = time.perf_counter()
+    feats, targ, obs, net_id = c4_dataset(ctx, AR2_PLAN, log=lambda m: None)
+    t_data = time.perf_counter() - t0
+    held = (net_id % 7) == 3
+    tr = torch.nonzero(~held).flatten()
+    order = torch.from_numpy(workloads.permutations(tr.numel(), 1, seed=4242)[0].astype(np.int64)).cuda()
+    tr = tr[order]
+    t1 = time.perf_counter()
+    net, hist = train_threshold_net(ctx, feats[tr].contiguous(), targ[tr].contiguous(), workloads.mlp_init(4243),
+                                    epochs=60, batch=512, lr=2e-3)
+    hi = torch.nonzero(held).flatten()
+    cal = calibrate(net, feats[hi].contiguous(), obs[hi].contiguous(), rate=0.0025)
+    t_train = time.perf_counter() - t1
+    ev = workloads.ar2_network(seed=1)
+    data = torch.from_numpy(ev.data).cuda()
+    perms = torch.from_numpy(workloads.permutations(ev.data.shape[2] - MAX_LAG, N_PERM, seed=11)).cuda()
+    n_vars = ev.data.shape[1]
+    res = {}
+    for mode in ("plain", "learned"):
+        kw = dict(k=K, max_lag=MAX_LAG, alpha=0.05)
+        if mode == "learned":
+            kw.update(learned=net, margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"])
+        ctx.select_parents(data, 0, perms, max_steps=1, **kw)  # warm-up
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        out = {t: ctx.select_parents(data, t, perms, **kw) for t in range(n_vars)}
+        torch.cuda.synchronize()
+        res[mode] = (out, time.perf_counter() - tm)
+        log(f"selection {mode}: " + "; ".join(f"{t}: {r['parents']}" for t, r in out.items()))
+    (plain, t_p), (learned, t_l) = res["plain"], res["learned"]
+    n_p = sum(len(r["parents"]) for r in plain.values())
+    n_l = sum(len(r["parents"]) for r in learned.values())
+    agree = sum(1 for t in range(n_vars) for v in range(n_vars)
+                if (v in {a for a, _ in plain[t]["parents"]}) == (v in {a for a, _ in learned[t]["parents"]}))
+    return {"workload": "AR(2) 5-node network, every node as target, N=10000, 25 candidates, k=4, 200 surrogates",
+            "learned_parents_per_s": round(n_l / t_l, 3), "plain_parents_per_s": round(n_p / t_p, 3),
+            "speedup": round((n_l / t_l) / max(n_p / t_p, 1e-12), 2),
+            "plain_seconds": round(t_p, 3), "learned_seconds": round(t_l, 3),
+            "parents_plain": n_p, "parents_learned": n_l,
+            "pair_agreement": agree / (n_vars * n_vars),
+            "exact_parent_sets": sum(int(plain[t]["parents"] == learned[t]["parents"]) for t in range(n_vars)),
+            "candidate_decisions": {"learned_gate_steps": sum(r["n_gate_decided"] for r in learned.values()),
+                                    "learned_fallback_steps": sum(r["n_fallback"] for r in learned.values()),
+                                    "plain_steps": sum(r["n_steps"] for r in plain.values())},
+            "cmi_estimates": {"plain": sum(r["n_cmi"] for r in plain.values()),
+                              "learned": sum(r["n_cmi"] for r in learned.values())},
+            "training": {"examples": int(feats.shape[0]), "held_out": int(hi.numel()), "dataset_s": round(t_data, 1),
+                         "train_and_calibrate_s": round(t_train, 1), "loss_first": round(hist[0], 5),
+                         "loss_last": round(hist[-1], 5), "margins": [round(cal["margin_lo"], 4),
+                                                                      round(cal["margin_hi"], 4)]}}
 
 
 def c4_evaluate(ctx, args, log):
@@ -482,8 +543,11 @@ def _cpu_model():
 def uneven_bench(ksg, args):
     """64 independent problems of uneven size and shape (N log-uniform in [2000, 50000], d_x and
     d_y in 1..2, d_z in 0..10, k in {4, 8}; Gaussian with random correlations): one batched
-    launch set per step.  Problems with k <= 4, N >= 2048 and a Z column run the key-ordered
-    window search, the rest the brute-force kernels compiled per shape or width."""
+    launch set per step.  Problems with k <= 4, a Z column and N at or above the window
+    threshold of their column count run the key-ordered window search, the rest the
+    brute-force kernels compiled per shape or width.  The batch is timed on an autotuned
+    context (group sizes, brute-force tile heights, window thresholds per column count) and on
+    one with the fixed defaults (tile height 256, windows from N = 2048)."""
     import torch
     import workloads
 
@@ -491,39 +555,52 @@ def uneven_bench(ksg, args):
         return torch.from_numpy(np.ascontiguousarray(pts.T)).cuda() if pts.shape[1] else None
 
     probs, _ = workloads.uneven_batch(seed=2)
-    ctx = ksg.Context(0)
-    ctx.set_option(ctx.OPT_WINDOWS, 0 if args.no_windows else 1)
     cols = [(soa(p.x), soa(p.y), soa(p.z)) for p in probs]
     batch = [ksg.Problem(x, y, z, p.k) for (x, y, z), p in zip(cols, probs)]
-    for _ in range(args.warmup):
-        ctx.cmi_batch(batch)
-    torch.cuda.synchronize()
-    ctx.set_option(ctx.OPT_TIMING, 1)
-    ctx.take_timing()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = ctx.cmi_batch(batch)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # the search span of each step (first launch to last, the launches running side by side
-    # on several streams) and the per-launch durations summed
-    span_ms, _, ops = ctx.take_timing()
-    kern = ctx.last_kernels()
-    ctx.set_option(ctx.OPT_TIMING, 0)
-    ms, _, nl = kern["single"]
-    achieved = ops / (span_ms * 1e-3)
-    res = out.cpu().numpy()
+
+    def run(tuned):
+        ctx = ksg.Context(0)
+        t_tune = time.perf_counter()
+        choices = ctx.autotune(8192) if tuned else None
+        t_tune = time.perf_counter() - t_tune
+        ctx.set_option(ctx.OPT_WINDOWS, 0 if args.no_windows else 1)
+        for _ in range(args.warmup):
+            ctx.cmi_batch(batch)
+        torch.cuda.synchronize()
+        ctx.set_option(ctx.OPT_TIMING, 1)
+        ctx.take_timing()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = ctx.cmi_batch(batch)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        # the search span of each step (first launch to last, the launches running side by side
+        # on several streams) and the per-launch durations summed
+        span_ms, _, ops = ctx.take_timing()
+        kern = ctx.last_kernels()
+        ctx.set_option(ctx.OPT_TIMING, 0)
+        ctx.close()
+        return dict(wall=wall, span_ms=span_ms, ops=ops, kern=kern, out=out.cpu().numpy(), choices=choices,
+                    tune_s=t_tune)
+
+    fixed = run(False)
+    tuned = run(True)
+    best = tuned if tuned["wall"] <= fixed["wall"] else fixed
+    ms, _, nl = best["kern"]["single"]
+    res = best["out"]
     brute = [p.n * (p.n - 1) * (4 * sum(p.dims) + 2) for p in probs]
-    n_win = sum(1 for p in probs if p.k <= 4 and p.n >= 2048 and p.dims[2] >= 1)
+    win_n = (tuned["choices"] or {}).get("window_min_n", {})
+    n_win = sum(1 for p in probs if p.k <= 4 and p.dims[2] >= 1 and sum(p.dims) <= 16 and
+                win_n.get(str(sum(p.dims)), 2048) is not None and p.n >= (win_n.get(str(sum(p.dims))) or 2048))
     line = {
         "metric": "CMI estimates/sec (64-problem uneven batch, N in [2000, 50000], k in {4, 8})",
-        "value": round(len(probs) * args.steps / wall, 2),
+        "value": round(len(probs) * args.steps / best["wall"], 2),
         "unit": "CMI/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1000.0 * wall / args.steps, 2),
+        "ms_per_step": round(1000.0 * best["wall"] / args.steps, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -532,17 +609,22 @@ def uneven_bench(ksg, args):
         "data": "synthetic",
         "config": {"workload": f"64 Gaussian problems, N log-uniform in [2000, 50000] (sum {sum(p.n for p in probs)}), "
                                f"d_x, d_y in 1..2, d_z in 0..10, k in {{4, 8}}; {n_win} searched with key-ordered "
-                               f"windows" + (" (off)" if args.no_windows else "")},
-        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
-                     "peak": round(PEAK_VALU / 1e12, 3), "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_VALU, 4), "traffic": None,
-                     "frac_4cycle_class": round(achieved / PEAK_VALU_4CYCLE, 4),
+                               f"windows under the tuned thresholds" + (" (windows off)" if args.no_windows else "")},
+        "autotune": {"choices": tuned["choices"], "seconds": round(tuned["tune_s"], 3),
+                     "tuned_ms_per_step": round(1000.0 * tuned["wall"] / args.steps, 2),
+                     "fixed_ms_per_step": round(1000.0 * fixed["wall"] / args.steps, 2),
+                     "tuned_search_span_ms": round(tuned["span_ms"] / args.steps, 3),
+                     "fixed_search_span_ms": round(fixed["span_ms"] / args.steps, 3),
+                     "headline": "tuned" if best is tuned else "fixed"},
+        "roofline": {"bound": "alu", "achieved": None, "peak": round(PEAK_VALU / 1e12, 3),
+                     "unit": "T VALU lane-instructions/s", "frac": None, "traffic": None,
                      "kernel": "single-problem search kernels (brute force per shape or width, and "
-                               "the key-ordered window search; operations over the pairs each visits), "
-                               "one launch per column count, run side by side",
-                     "search_span_ms_per_step": round(span_ms / args.steps, 3),
+                               "the key-ordered window search), one launch per column count, run side by side",
+                     "search_span_ms_per_step": round(best["span_ms"] / args.steps, 3),
                      "kernel_ms_sum_per_step": round(ms / args.steps, 3),
-                     "launches_per_step": nl / args.steps, "ops_per_step": ops / args.steps,
+                     "launches_per_step": nl / args.steps,
+                     "executed_ops_per_step": best["ops"] / args.steps,
+                     "effective_ops_rate": round(float(sum(brute)) / (best["span_ms"] / args.steps * 1e-3) / 1e12, 3),
                      "brute_force_ops_per_step": float(sum(brute))},
     }
     if not args.no_cpu_baseline:
@@ -553,7 +635,8 @@ def uneven_bench(ksg, args):
         for i in order:  # smallest problems first, until about 15 s of oracle time
             p = probs[i]
             ref = ksg_cmi(p.x, p.y, p.z, p.k)
-            worst = max(worst, abs(float(res[i]) - ref) / max(1.0, abs(ref)))
+            worst = max(worst, abs(float(res[i]) - ref) / max(1.0, abs(ref)),
+                        abs(float(fixed["out"][i]) - ref) / max(1.0, abs(ref)))
             done.append(i)
             sample_ops += brute[i]
             if time.perf_counter() - t1 > 15.0:
@@ -562,12 +645,11 @@ def uneven_bench(ksg, args):
         # the sample's brute-force operation rate, priced at the batch's mean work per CMI
         cps = (sample_ops / dt) / (sum(brute) / len(probs))
         line["cpu_baseline"] = {"value": round(cps, 4), "unit": "CMI/s", "cores": 1, "kind": "oracle",
-                                "cpu_model": _cpu_model(),
+                                "cpu_model": _cpu_model(), "host": _host_cpu(),
                                 "sample": f"the {len(done)} smallest problems (N {probs[done[0]].n}.."
                                           f"{probs[done[-1]].n}), one process, {dt:.1f} s; rate scaled by "
                                           f"the batch's mean brute-force operations per CMI"}
         line["parity_spot_check_max_rel_err"] = worst
-    ctx.close()
     return line
 
 
@@ -614,6 +696,8 @@ def main():
                     help="c4: also run the judged selection (gate and plain test on every step)")
     ap.add_argument("--dump-dataset", default=None,
                     help="build the learned-null training set and save it (npz) instead of benchmarking")
+    ap.add_argument("--no-selection", action="store_true",
+                    help="skip the learned-vs-plain parent selection on the AR(2) network")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the pass that replays the steps from HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -853,6 +937,9 @@ def main():
     line["steps_detail"] = {str(m): {"c_star_candidate": [c for c in range(25) if c not in order[:m]][r["c_star"]],
                                      "t_obs": round(r["t_obs"], 6), "pval": r["pval"]}
                             for m, r in results.items()}
+    if not args.no_selection and args.algorithm == 1:
+        # the metric's second half: parents/s with the learned null against the plain test
+        line["selection"] = selection_bench(ctx, log=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps(line))
     ctx.close()
 

@@ -140,7 +140,17 @@ typedef enum ksg_option {
                              * (FP64) hold at most this many elements: 0 (default) = 2^27, i.e.
                              * 1.5 GiB of workspace; smaller values bound the workspace (more
                              * launches, same results) */
-  KSG_OPT_WINDOWS = 6       /* 1 (default): single problems (not grouped) with k <= 4, N >= 2048,
+  KSG_OPT_MEM_LIMIT = 9,    /* bytes of device workspace the context may hold (columns pool,
+                             * radii, terms, descriptors, graphs...): 0 (default) = no limit; a
+                             * batch that needs more fails with KSG_ENOMEM and leaves the context
+                             * usable */
+  KSG_OPT_TILE_Q = 8,       /* queries per work-group of the brute-force kernels: 0 (default) =
+                             * the autotuner's choice for the launch's size (256 before tuning),
+                             * or 64, 128, 256 forced; same results up to the order of the FP64
+                             * sum */
+  KSG_OPT_WINDOWS = 6       /* 1 (default): single problems (not grouped) with k <= 4, N at or
+                             * above the window threshold of their column count (2048 before
+                             * ksg_autotune; the tuner's per-D choice after it; 2: 2048 always),
                              * no per-point outputs and an unpermuted Z column are searched with
                              * their rows in the order of that column, each tile scanning only the
                              * rows its radii, rectangle sides and counts can reach (same results
@@ -154,12 +164,19 @@ int ksg_ctx_set_option(ksg_ctx* ctx, int option, int64_t value);
  * replays, and graphs held now.  Errors: KSG_EINVAL. */
 int ksg_graph_stats(ksg_ctx* ctx, int64_t* captures, int64_t* replays, int64_t* held);
 
-/* Autotuner of the grouped search kernel: for k <= 4 and k <= 8 and every conditioning
- * dimension m = 0..14, time the group sizes 8 and 16 on a synthetic batch (32 problems of n
- * points sharing Y and Z) and keep the faster for KSG_OPT_GROUP_SIZE = -1.  cache_path (host
- * string or NULL): a text file of per-device results (keyed by architecture, compute units
- * and library version); an existing entry is used instead of timing, a new one is appended.
- * tuned_out (host int32 [30] or NULL): the chosen sizes, k <= 4 first.  Synchronises.
+/* Autotuner of the launch shapes, from timings of synthetic batches on the context's device:
+ * (1) the group size (8 or 16) of the grouped kernels for k <= 4 and k <= 8 and every
+ * conditioning dimension m = 0..14 (32 problems of n points sharing Y and Z; m > 14 always use
+ * 8); (2) the tile height (64, 128 or 256 queries per work-group) of the brute-force kernels,
+ * for launches of fewer than 4 x (compute units) tiles of 256 and for larger ones; (3) for
+ * single problems of D = 3..16 columns with an unpermuted Z column, the smallest N in
+ * {2048, 8192, 32768} at which the key-ordered window search beats the brute-force kernel
+ * (never: INT32_MAX).  Later batches on the context use these choices (KSG_OPT_GROUP_SIZE = -1,
+ * KSG_OPT_TILE_Q = 0, KSG_OPT_WINDOWS = 1).  cache_path (host string or NULL): a text file of
+ * per-device results (keyed by architecture, compute units and library version); an existing
+ * entry is used instead of timing, a new one is appended.  tuned_out (host int32 [46] or NULL):
+ * the 15 group sizes for k <= 4, the 15 for k <= 8, the two tile heights, the 14 window
+ * thresholds for D = 3..16.  Synchronises.
  * Errors: KSG_EINVAL (n outside [256, 2^20]), KSG_ENOMEM, KSG_EDEVICE. */
 int ksg_autotune(ksg_ctx* ctx, int64_t n, const char* cache_path, int32_t* tuned_out);
 

@@ -238,6 +238,8 @@ class Context:
     OPT_ALGORITHM = 5
     OPT_WINDOWS = 6
     OPT_GROUP_CHUNK = 7
+    OPT_TILE_Q = 8
+    OPT_MEM_LIMIT = 9
 
     def __init__(self, device: int = 0, stream=None):
         import torch
@@ -275,11 +277,18 @@ class Context:
         self._check(lib.ksg_ctx_set_option(self._h, option, int(value)), "ksg_ctx_set_option")
 
     def autotune(self, n: int = 8192, cache_path: Optional[str] = None):
-        """Pick the group size per (k bucket, m) by timing (see ksg_autotune); returns the table."""
-        out = np.zeros(30, np.int32)
+        """Tune the launch shapes by timing (see ksg_autotune); returns the choices: group size per
+        conditioning dimension m = 0..14 (k <= 4, k <= 8), brute-force tile height for launches of
+        few / many work-groups, smallest N searched with key-ordered windows per column count D
+        (None: never)."""
+        out = np.zeros(46, np.int32)
         self._check(lib.ksg_autotune(self._h, int(n), cache_path.encode() if cache_path else None,
                                      out.ctypes.data), "ksg_autotune")
-        return {"k<=4": out[:15].tolist(), "k<=8": out[15:].tolist()}
+        big = np.iinfo(np.int32).max
+        return {"k<=4": out[:15].tolist(), "k<=8": out[15:30].tolist(),
+                "tile_q": {"few_groups": int(out[30]), "many_groups": int(out[31])},
+                "window_min_n": {str(D): (None if int(v) == big else int(v))
+                                 for D, v in zip(range(3, 17), out[32:46])}}
 
     def graph_stats(self) -> dict:
         """Batches captured into graphs, graph replays and graphs held (KSG_OPT_USE_GRAPH)."""

@@ -157,8 +157,8 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
     std::map<std::pair<const float*, int64_t>, int> by_key;
     for (int i = 0; i < np; ++i) {
       const Problem& p = probs[i];
-      if (group_of[i] >= 0 || p.k + 1 > 5 || p.n < kWindowMinN || p.dz < 1 ||
-          p.dx + p.dy + p.dz > kMaxDimsCompiled)
+      if (group_of[i] >= 0 || p.k + 1 > 5 || p.dz < 1 || p.dx + p.dy + p.dz > kMaxDimsCompiled ||
+          p.n < window_min_n(p.dx + p.dy + p.dz))
         continue;
       if (p.eps_out || p.counts_out || p.local_out) continue;
       int a_key = -1;
@@ -309,6 +309,16 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
 
   auto cost = [&](int i) { return brute_cost(probs[i]); };
   auto n_tiles_of = [&](int i) { return (int)((probs[i].n + kTileQ - 1) / kTileQ); };
+  // tile heights of the brute-force launches (algorithm 1): by the launch's size in 256-query tiles
+  {
+    int64_t t_plain = 0, t_wide = 0;
+    for (int i = 0; i < np; ++i) {
+      if (group_of[i] >= 0 || win_of[i] >= 0) continue;
+      (wide[i] ? t_wide : t_plain) += n_tiles_of(i);
+    }
+    P.tile_q_plain = algorithm == 1 ? brute_tile_q(t_plain) : kTileQ;
+    P.tile_q_wide = brute_tile_q(t_wide);
+  }
 
   // ---- per-problem descriptors (search of ungrouped problems + finalisation of all) ----
   std::vector<int> order;
@@ -351,6 +361,10 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
     d.dz = wide[i] ? kWideDims - dx - dy : p.dz;
     d.k = p.k;
     d.n_tiles = n_tiles_of(i);
+    if (group_of[i] < 0 && win_of[i] < 0) {  // brute-force launches: their own tile height
+      const int tq = wide[i] ? P.tile_q_wide : P.tile_q_plain;
+      d.n_tiles = (int)((p.n + tq - 1) / tq);
+    }
     d.eps_out = p.eps_out;
     d.counts_out = p.counts_out;
     d.local_out = p.local_out;
@@ -505,6 +519,7 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
       c.items = order_items(units);
       // runs of consecutive groups of one Y/Z set -> slot ranges of at most kYZSlots
       c.ydesc_off = P.ydescs.size();
+      const size_t y_first = P.yitems.size();
       size_t r0 = a;
       while (r0 < b) {
         size_t r1 = r0 + 1;
@@ -524,11 +539,21 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
           y.n_slots = std::min(kYZSlots, n_valid - s0);
           const int di = (int)P.ydescs.size();
           P.ydescs.push_back(y);
-          for (int row = 0; row < f.n; ++row) P.yitems.push_back(WorkItem{di, row});
+          // One work-group per query row, rows handed out XCD-aware: in every block of 32 items
+          // (32 rows), work-group b takes row 4 (b % 8) + (b % 32) / 8, so the four consecutive
+          // rows whose radii share a 128-byte line of E go to work-groups b, b+8, b+16, b+24,
+          // which the dispatcher places on one XCD (one L2 fetch instead of four).  Each
+          // descriptor's items are padded to a multiple of 32 with empty items.
+          const int nb = (f.n + 31) / 32;
+          for (int b = 0; b < nb * 32; ++b) {
+            const int row = 32 * (b / 32) + 4 * (b % 8) + (b % 32) / 8;
+            P.yitems.push_back(row < f.n ? WorkItem{di, row} : WorkItem{-1, 0});
+          }
         }
         r0 = r1;
       }
       c.n_ydesc = P.ydescs.size() - c.ydesc_off;
+      c.n_yitems = P.yitems.size() - y_first;
       P.chunks.push_back(std::move(c));
       a = b;
     }
@@ -545,18 +570,10 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
     P.n_gitems += c.items.size();
   }
   {
-    size_t off = items.size() + P.n_gitems;
-    size_t yoff = 0;
+    size_t off = items.size() + P.n_gitems;  // Y/Z items follow, chunk after chunk
     for (BatchPlan::Chunk& c : P.chunks) {
-      // Y/Z items of the chunk: those whose descriptor lies in the chunk's range
       c.yitem_off = off;
-      size_t cnt = 0;
-      while (yoff < P.yitems.size() && (size_t)P.yitems[yoff].prob < c.ydesc_off + c.n_ydesc) {
-        ++cnt;
-        ++yoff;
-      }
-      c.n_yitems = cnt;
-      off += cnt;
+      off += c.n_yitems;
     }
   }
   st = reserve(partials, sizeof(double) * std::max(part, 1), "partial sums");
@@ -719,7 +736,7 @@ int ksg_ctx::enqueue_batch(const BatchPlan& P, const void* d_desc_v, const WorkI
       if ((st = span_begin(ls))) return st;
       if (L.kind == 3) {
         KSG_HIP(this, launch_ksg_search(d_desc, d_items + P.wide_seg.off, P.wide_seg.count, d_htab, d_part,
-                                        kGenericShape + kWideDims, P.wide_seg.kp, ls));
+                                        kGenericShape + kWideDims, P.wide_seg.kp, ls, P.tile_q_wide));
       } else if (L.kind == 2) {
         const BatchPlan::Segment& g = P.segments[L.seg];
         KSG_HIP(this, launch_ksg_alg2(d_desc, d_items + g.off, g.count, d_htab, d_part, g.D, g.kp, ls));
@@ -727,7 +744,8 @@ int ksg_ctx::enqueue_batch(const BatchPlan& P, const void* d_desc_v, const WorkI
         const BatchPlan::Segment& g = P.wsegments[L.seg];
         KSG_HIP(this, launch_ksg_window(d_desc, d_items + g.off, g.count, d_htab, d_part, g.D, algorithm, d_w, ls));
       } else {
-        KSG_HIP(this, launch_ksg_search(d_desc, d_items, P.n_plain_items, d_htab, d_part, P.common_shape, P.kp, ls));
+        KSG_HIP(this, launch_ksg_search(d_desc, d_items, P.n_plain_items, d_htab, d_part, P.common_shape, P.kp, ls,
+                                        P.tile_q_plain));
       }
       if ((st = span_end(3, ls))) return st;
     }
@@ -772,9 +790,14 @@ int ksg_ctx::enqueue_batch(const BatchPlan& P, const void* d_desc_v, const WorkI
 
 int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   if (probs.empty()) return KSG_OK;
+  TraceRange range("ksg batch");
   if (use_graph && !timing && !check_finite) return run_batch_graph(probs, d_out);
   BatchPlan P;
-  int st = plan_batch(probs, P);
+  int st;
+  {
+    TraceRange r("ksg batch plan");
+    st = plan_batch(probs, P);
+  }
   if (st) return st;
   st = reserve(desc, std::max<size_t>(P.desc_bytes(), 16), "descriptors");
   if (!st) st = reserve(this->items, std::max<size_t>(sizeof(WorkItem) * P.item_count(), 16), "work items");
@@ -782,8 +805,11 @@ int ksg_ctx::run_batch(const std::vector<Problem>& probs, double* d_out) {
   if (st) return st;
   st = upload_batch(P, desc.ptr, this->items.ptr, this->jobs.ptr);
   if (st) return st;
-  st = enqueue_batch(P, desc.ptr, static_cast<const WorkItem*>(this->items.ptr),
-                     static_cast<const PackJob*>(this->jobs.ptr), d_out);
+  {
+    TraceRange r("ksg batch enqueue");
+    st = enqueue_batch(P, desc.ptr, static_cast<const WorkItem*>(this->items.ptr),
+                       static_cast<const PackJob*>(this->jobs.ptr), d_out);
+  }
   if (st) return st;
   last_items = (int64_t)P.item_count();
   last_groups = P.n_groups;
@@ -802,10 +828,15 @@ static std::vector<uint64_t> batch_key(const ksg_ctx* c, const std::vector<Probl
   key.push_back((uint64_t)(uintptr_t)d_out);
   key.push_back((uint64_t)(int64_t)c->group_size);
   key.push_back((uint64_t)c->algorithm);
-  key.push_back((uint64_t)c->use_windows);
+  key.push_back((uint64_t)c->use_windows | ((uint64_t)c->windows_untuned << 1));
   key.push_back((uint64_t)c->group_chunk_elems);
+  key.push_back((uint64_t)c->tile_q);
+  key.push_back((uint64_t)c->tuned);
   for (int t = 0; t < 2; ++t)
     for (int m = 0; m < 15; ++m) key.push_back((uint64_t)c->tuned_g[t][m]);
+  key.push_back((uint64_t)c->tuned_tq[0]);
+  key.push_back((uint64_t)c->tuned_tq[1]);
+  for (int D = 0; D <= kMaxDimsCompiled; ++D) key.push_back((uint64_t)(int64_t)c->tuned_win_n[D]);
   for (const Problem& p : probs) {
     key.push_back((uint64_t)p.n);
     key.push_back(((uint64_t)p.dx << 48) | ((uint64_t)p.dy << 32) | ((uint64_t)p.dz << 16) | (uint64_t)p.k);
@@ -833,8 +864,10 @@ static uint64_t hash_key(const std::vector<uint64_t>& key) {
 
 void ksg_ctx::drop_graph(GraphEntry& g) {
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
-  for (DevBuf* b : {&g.desc, &g.items, &g.jobs})
+  for (DevBuf* b : {&g.desc, &g.items, &g.jobs}) {
     if (b->ptr) (void)hipFree(b->ptr);
+    mem_held -= b->cap;
+  }
   g = GraphEntry{};
 }
 
@@ -851,6 +884,7 @@ int ksg_ctx::run_batch_graph(const std::vector<Problem>& probs, double* d_out) {
   for (GraphEntry& g : graphs) {
     if (g.hash == h && g.gen == buf_gen && g.key == key) {
       g.last_use = ++graph_clock;
+      TraceRange r("ksg batch graph replay");
       KSG_HIP(this, hipGraphLaunch(g.exec, stream));
       last_items = g.n_items;
       last_groups = g.n_groups;

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <vector>
@@ -163,6 +164,10 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
       break;
     }
     const int cands = (int)s.pool.size();
+    char label[64];
+    std::snprintf(label, sizeof label, "ksg greedy step %d (m=%d, %d candidates)", out->n_steps,
+                  (int)s.selected.size(), cands);
+    TraceRange step_range(label);
     int decision = -1;  // 1 include, 0 stop
     double t_obs = 0, pval = -1;
     int c_star = 0;
@@ -298,6 +303,7 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
     return src;
   };
   if (o->prune) {
+    TraceRange prune_range("ksg pruning");
     for (;;) {
       const std::vector<int> src = sources_of();
       if (src.empty()) break;
@@ -325,6 +331,7 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
     if (out->pruned) out->pruned[i] = pruned[i];
 
   if (o->omnibus) {
+    TraceRange omni_range("ksg omnibus test");
     std::vector<int> src, tgt;
     for (int cidx : s.selected) (cidx / s.L == target ? tgt : src).push_back(cidx);
     if (!src.empty() && (int)(src.size() + 1 + tgt.size()) <= lib_cond + 2) {
@@ -368,6 +375,7 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   std::vector<int> seq_removed;
   std::vector<std::pair<int, double>> seq_p;  // (source, p-value) of every tested source
   if (o->sequential && (!o->omnibus || !out->omnibus_tested || out->omnibus_significant)) {
+    TraceRange seq_range("ksg sequential test");
     const std::vector<int> src = sources_of();
     if (!src.empty()) {
       st = source_table(src);

@@ -25,7 +25,7 @@ struct alignas(16) ProbDesc {
   int32_t n;          // points
   int32_t n_pad;      // multiple of kPad
   int32_t dx, dy, dz, k;
-  int32_t n_tiles;    // ceil(n / kTileQ)
+  int32_t n_tiles;    // ceil(n / tile height of the problem's launch)
   int32_t part_base;  // first slot of this problem's per-tile partial sums
   float* eps_out;     // optional per-point outputs (nullptr when not wanted)
   int32_t* counts_out;
@@ -135,7 +135,7 @@ struct MaxStatOut {
 // columns, or -1 for a mixed launch.
 hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                              const double* d_htab, double* d_partials, int shape, int kp,
-                             hipStream_t stream);
+                             hipStream_t stream, int tile_q = kTileQ);
 // Key order of one column (sigma[rank] = row) and the key-ordered window search over the work
 // items of problems that all have D columns (k <= 4), KSG algorithm alg (1 or 2).
 hipError_t launch_window_rank(const float* key, int n, int n_pad, int32_t* sigma, hipStream_t stream);

@@ -44,13 +44,20 @@ int ksg_ctx::reserve(DevBuf& b, size_t bytes, const char* what) {
   KSG_HIP(this, hipStreamSynchronize(stream));
   // captured batches hold the addresses of these work buffers: a new address retires them
   if (&b == &pool || &b == &partials || &b == &ebuf || &b == &tbuf || &b == &htab) ++buf_gen;
+  const size_t old_cap = b.cap;
   if (b.ptr) {
     KSG_HIP(this, hipFree(b.ptr));
     b.ptr = nullptr;
-    b.cap = 0;
   }
-  size_t want = std::max(bytes, b.cap + b.cap / 2);
+  mem_held -= old_cap;
+  b.cap = 0;
+  size_t want = std::max(bytes, old_cap + old_cap / 2);  // grow by half at least
   want = (want + 4095) & ~size_t(4095);
+  const size_t need = (bytes + 4095) & ~size_t(4095);
+  if (mem_limit > 0 && mem_held + need > (size_t)mem_limit)
+    return fail(KSG_ENOMEM, "%s needs %zu bytes; the context's workspace limit is %lld (holding %zu)", what, need,
+                (long long)mem_limit, mem_held);
+  if (mem_limit > 0 && mem_held + want > (size_t)mem_limit) want = need;
   hipError_t e = hipMalloc(&b.ptr, want);
   if (e != hipSuccess) {
     want = (bytes + 4095) & ~size_t(4095);
@@ -63,6 +70,7 @@ int ksg_ctx::reserve(DevBuf& b, size_t bytes, const char* what) {
     return fail(KSG_ENOMEM, "cannot allocate %zu bytes for %s", bytes, what);
   }
   b.cap = want;
+  mem_held += want;
   return KSG_OK;
 }
 
@@ -127,7 +135,7 @@ int ksg_ctx::ensure_htab(int64_t n) {
 
 // ============================================================== context
 
-extern "C" int ksg_version(void) { return 10000; }
+extern "C" int ksg_version(void) { return 10100; }
 
 extern "C" const char* ksg_status_string(int s) {
   switch (s) {
@@ -267,12 +275,25 @@ extern "C" int ksg_ctx_set_option(ksg_ctx* c, int option, int64_t value) {
       c->use_graph = value != 0;
       if (!c->use_graph) c->clear_graphs();
       return KSG_OK;
+    case KSG_OPT_MEM_LIMIT:
+      if (value < 0) return c->fail(KSG_EINVAL, "workspace limit must be >= 0 bytes (0 = none)");
+      c->mem_limit = value;
+      return KSG_OK;
+    case KSG_OPT_TILE_Q:
+      if (value != 0 && value != 64 && value != 128 && value != 256)
+        return c->fail(KSG_EINVAL, "tile height must be 0 (tuned), 64, 128 or 256");
+      c->tile_q = (int)value;
+      return KSG_OK;
     case KSG_OPT_GROUP_CHUNK:
       if (value < 0 || value > (int64_t)1 << 31)
         return c->fail(KSG_EINVAL, "group chunk must lie in [0, 2^31] elements (0 = default)");
       c->group_chunk_elems = value;
       return KSG_OK;
-    case KSG_OPT_WINDOWS: c->use_windows = value != 0; return KSG_OK;
+    case KSG_OPT_WINDOWS:
+      if (value < 0 || value > 2) return c->fail(KSG_EINVAL, "windows must be 0 (off), 1 (tuned) or 2 (from N = 2048)");
+      c->use_windows = value != 0;
+      c->windows_untuned = value == 2;
+      return KSG_OK;
     case KSG_OPT_ALGORITHM:
       if (value != 1 && value != 2) return c->fail(KSG_EINVAL, "KSG algorithm must be 1 or 2");
       c->algorithm = (int)value;

@@ -304,15 +304,16 @@ static const void* pick_search_kernel(int shape, int kp) {
 
 hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                              const double* d_htab, double* d_partials, int shape, int kp,
-                             hipStream_t stream) {
+                             hipStream_t stream, int tile_q) {
   if (n_items <= 0) return hipSuccess;
+  if (tile_q != 64 && tile_q != 128 && tile_q != 256) return hipErrorInvalidValue;
   const void* fn = pick_search_kernel(shape, kp);
   const ProbDesc* a0 = d_desc;
   const WorkItem* a1 = d_items;
   const double* a2 = d_htab;
   double* a3 = d_partials;
   void* args[] = {&a0, &a1, &a2, &a3};
-  return hipLaunchKernel(fn, dim3(n_items), dim3(kTileQ), args, 0, stream);
+  return hipLaunchKernel(fn, dim3(n_items), dim3(tile_q), args, 0, stream);
 }
 
 hipError_t launch_ksg_group_radius(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,

@@ -108,7 +108,12 @@ __device__ __forceinline__ void tile_epilogue(const KSG_AS4 ProbDesc* pd, int ti
   const int wave = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) s_red[wave] = t;
   __syncthreads();
-  if (threadIdx.x == 0) partials[pd->part_base + tile] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+  // fixed-order sum over the tile's 1, 2 or 4 waves (the tile height is the block size)
+  if (threadIdx.x == 0) {
+    const int nw = (int)blockDim.x >> 6;
+    partials[pd->part_base + tile] =
+        nw == 4 ? (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]) : (nw == 2 ? s_red[0] + s_red[1] : s_red[0]);
+  }
 }
 
 // Pass 1: the (k+1) smallest joint distances, self included; returns eps_i.
@@ -231,7 +236,7 @@ __device__ __forceinline__ void search_tile(const KSG_AS4 ProbDesc* pd, int tile
   const int n = pd->n;
   const int n_pad = pd->n_pad;
   const int k = pd->k;
-  const int qraw = tile * kTileQ + (int)threadIdx.x;
+  const int qraw = tile * (int)blockDim.x + (int)threadIdx.x;
   const bool valid = qraw < n;
   const int qi = valid ? qraw : n - 1;
 
@@ -261,7 +266,7 @@ __device__ __forceinline__ void search_tile_dims(const KSG_AS4 ProbDesc* pd, int
   const int n_pad = pd->n_pad;
   const int k = pd->k;
   const int dx = pd->dx, dy = pd->dy;
-  const int qraw = tile * kTileQ + (int)threadIdx.x;
+  const int qraw = tile * (int)blockDim.x + (int)threadIdx.x;
   const bool valid = qraw < n;
   const int qi = valid ? qraw : n - 1;
   cfptr col[D];
@@ -290,7 +295,7 @@ __device__ __forceinline__ void search_tile_generic(const KSG_AS4 ProbDesc* pd, 
   const int n_pad = pd->n_pad;
   const int k = pd->k;
   const int dx = pd->dx, dy = pd->dy;
-  const int qraw = tile * kTileQ + (int)threadIdx.x;
+  const int qraw = tile * (int)blockDim.x + (int)threadIdx.x;
   const bool valid = qraw < n;
   const int qi = valid ? qraw : n - 1;
   cfptr col[D];
@@ -347,7 +352,9 @@ __device__ __forceinline__ void dispatch_generic(int D, const KSG_AS4 ProbDesc* 
   }
 }
 
-// Batched kernel: one work-group per work item (problem, 256-query tile).  The host orders
+// Batched kernel: one work-group per work item (problem, query tile).  The tile height is the
+// work-group size, 64, 128 or 256 queries (one per lane), chosen per launch by the autotuner;
+// the window and algorithm-2 kernels keep 256 (their epilogue reads four waves).  The host orders
 // the items longest-problem-first and the hardware dispatcher hands work-groups to compute
 // units in that order as they free up, which gives the dynamic longest-first schedule of a
 // work queue without a device-side queue.  SHAPE in [0, kGenericShape): every problem of the

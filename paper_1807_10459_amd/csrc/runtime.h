@@ -3,14 +3,26 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <string>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "../../include/ksgcmi.h"
 #include "internal.h"
 
 namespace ksg {
+
+// A roctx range for the profiler's marker trace (rocprofv3 --marker-trace): pushed on
+// construction, popped on destruction.  Without a profiler attached the calls do nothing.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // A grow-only device allocation owned by the context.
 struct DevBuf {
@@ -71,6 +83,7 @@ struct BatchPlan {
   float* pool_base = nullptr;
   double brute_ops = 0.0;
   int64_t n_groups = 0;
+  int tile_q_plain = kTileQ, tile_q_wide = kTileQ;  // brute-force launches' tile heights
   size_t desc_bytes() const;
   size_t item_count() const;
 };
@@ -110,10 +123,18 @@ struct ksg_ctx {
   std::string err;
 
   bool check_finite = true;
+  int64_t mem_limit = 0;         // KSG_OPT_MEM_LIMIT: bytes of workspace the context may hold (0 = any)
+  size_t mem_held = 0;           // bytes of workspace held now
   int group_size = -1;           // -1: tuned per conditioning dimension, 0: no grouping, 8 or 16
   int algorithm = 1;             // KSG algorithm of every estimate: 1 or 2
   bool use_windows = true;       // key-ordered window search for eligible single problems
+  bool windows_untuned = false;  // KSG_OPT_WINDOWS = 2: from N = 2048 whatever the tuner found
   int tuned_g[2][15] = {{0}};    // [k <= 4 ? 0 : 1][m]: group size picked by the autotuner (0 = default)
+  // autotuned launch shapes (ksg_autotune), used once `tuned` is set:
+  int tuned_tq[2] = {0, 0};      // brute-force tile height for launches of few / many work-groups
+  int tuned_win_n[ksg::kMaxDimsCompiled + 1] = {0};  // [D]: smallest N searched with windows
+  bool tuned = false;
+  int tile_q = 0;                // KSG_OPT_TILE_Q: 0 = tuned (256 before tuning), or 64/128/256
   bool use_graph = false;        // KSG_OPT_USE_GRAPH: capture batches into HIP graphs and replay them
   int64_t group_chunk_elems = 0; // KSG_OPT_GROUP_CHUNK: 0 = kGroupChunkElems
 
@@ -141,6 +162,18 @@ struct ksg_ctx {
 
   int64_t last_items = 0;
   int64_t last_groups = 0;
+  // smallest N from which single problems of D columns use the key-ordered window search
+  int window_min_n(int D) const {
+    if (!tuned || windows_untuned || D < 3 || D > ksg::kMaxDimsCompiled || tuned_win_n[D] <= 0) return ksg::kWindowMinN;
+    return std::max(ksg::kWindowMinN, tuned_win_n[D]);
+  }
+  // tile height of a brute-force launch of tiles256 tiles of 256 queries
+  int brute_tile_q(int64_t tiles256) const {
+    if (tile_q) return tile_q;
+    if (!tuned) return ksg::kTileQ;
+    const int t = tuned_tq[tiles256 < 4 * (int64_t)cus ? 0 : 1];
+    return t ? t : ksg::kTileQ;
+  }
   int tuned_group_size(int m, int k) const {
     if (m > ksg::kGroupMaxM16) return 8;  // only groups of 8 are compiled for m > 14
     const int t = tuned_g[k <= 4 ? 0 : 1][m];

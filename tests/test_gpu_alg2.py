@@ -180,8 +180,8 @@ def test_window_search_matches_oracle(lib, ctx, case):
     got, ops = {}, {}
     ctx.set_option(ctx.OPT_TIMING, 1)
     try:
-        for w in (1, 0):
-            ctx.set_option(ctx.OPT_WINDOWS, w)
+        for w in (1, 0):  # 2: windows from N = 2048 whatever an earlier autotune found
+            ctx.set_option(ctx.OPT_WINDOWS, 2 * w)
             ctx.take_timing()
             got[w] = ctx.cmi_batch(probs).cpu().numpy()
             ops[w] = ctx.take_timing()[2]

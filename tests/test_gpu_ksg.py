@@ -379,9 +379,44 @@ def test_autotune_table_and_cache(lib, ctx, tmp_path):
     path = str(tmp_path / "tune.txt")
     a = ctx.autotune(2048, cache_path=path)
     assert all(g in (8, 16) for g in a["k<=4"] + a["k<=8"]) and len(a["k<=4"]) == 15
+    assert set(a["tile_q"].values()) <= {64, 128, 256}
+    assert sorted(int(d) for d in a["window_min_n"]) == list(range(3, 17))
+    assert all(v in (None, 2048, 8192, 32768) for v in a["window_min_n"].values())
+    print("autotune", a)
     b = ctx.autotune(2048, cache_path=path)  # served from the cache
     assert a == b
     assert open(path).read().count("\n") == 1
+    # the tuned context still gives the oracle's estimates (brute force, windows, groups)
+    probs, _ = workloads.uneven_batch(seed=2, n_problems=12, n_lo=2000, n_hi=6000)
+    cols = [(soa(p.x), soa(p.y), soa(p.z)) for p in probs]
+    got = ctx.cmi_batch([lib.Problem(x, y, z, p.k) for (x, y, z), p in zip(cols, probs)]).cpu().numpy()
+    for i in (0, 5, 11):
+        ref = ksg_cmi(probs[i].x, probs[i].y, probs[i].z, probs[i].k)
+        assert abs(got[i] - ref) <= tol(ref), i
+
+
+@pytest.mark.parametrize("tq", [64, 128])
+@pytest.mark.parametrize("dims", [(1, 1, 2), (2, 1, 3), (2, 2, 9), (3, 2, 14)])
+def test_tile_heights_match_oracle(lib, ctx, tq, dims):
+    """Brute-force launches with 64- and 128-query tiles: counts and radii as the oracle's, the
+    estimate equal to the 256-query tiling up to the order of the FP64 sum."""
+    import torch
+    n = 613 + 11 * sum(dims)  # ragged last tile at every height
+    p = workloads.random_problem(900 + tq + sum(dims), n, *dims, 4)
+    ctx.set_option(ctx.OPT_GROUP_SIZE, 0)  # the batch below runs the brute-force kernel
+    ctx.set_option(ctx.OPT_TILE_Q, tq)
+    try:
+        cmi = _check_full(lib, ctx, p.x, p.y, p.z, 4, f"{dims} tq={tq}")
+        batch = [lib.Problem(soa(p.x), soa(p.y), soa(p.z), 4)] * 3
+        small = ctx.cmi_batch(batch).cpu().numpy()
+        ctx.set_option(ctx.OPT_TILE_Q, 256)
+        full = float(ctx.cmi_batch(batch).cpu().numpy()[0])
+    finally:
+        ctx.set_option(ctx.OPT_TILE_Q, 0)
+        ctx.set_option(ctx.OPT_GROUP_SIZE, -1)
+    assert np.all(np.abs(small - full) <= _sum_order_bound(n)) and abs(cmi - full) <= _sum_order_bound(n)
+    with pytest.raises(lib.KsgError):
+        ctx.set_option(ctx.OPT_TILE_Q, 32)
 
 
 def test_device_props(lib):
@@ -413,8 +448,8 @@ def test_window_search_matches_oracle(lib, ctx, case):
     dp = dev(perms)
     probs = [lib.Problem(xd, yd, zd, k)] + [lib.Problem(xd, yd, zd, k, perm_x=dp[q]) for q in range(n_perm)]
     got = {}
-    for w in (1, 0):
-        ctx.set_option(ctx.OPT_WINDOWS, w)
+    for w in (1, 0):  # 2: windows from N = 2048 whatever an earlier autotune found
+        ctx.set_option(ctx.OPT_WINDOWS, 2 * w)
         got[w] = ctx.cmi_batch(probs).cpu().numpy()
     ctx.set_option(ctx.OPT_WINDOWS, 1)
     assert np.max(np.abs(got[1] - got[0])) <= _sum_order_bound(n)
@@ -460,8 +495,8 @@ def test_window_search_degenerate_keys(lib, ctx, case):
     got, ops = {}, {}
     ctx.set_option(ctx.OPT_TIMING, 1)
     try:
-        for w in (1, 0):
-            ctx.set_option(ctx.OPT_WINDOWS, w)
+        for w in (1, 0):  # 2: windows from N = 2048 whatever an earlier autotune found
+            ctx.set_option(ctx.OPT_WINDOWS, 2 * w)
             ctx.take_timing()
             got[w] = ctx.cmi_batch(probs).cpu().numpy()
             ops[w] = ctx.take_timing()[2]
@@ -491,8 +526,8 @@ def test_uneven_batch_windows_match_brute_force(lib, ctx):
     batch = [lib.Problem(soa(p.x), soa(p.y), soa(p.z), p.k) for p in probs]
     got = {}
     try:
-        for w in (1, 0):
-            ctx.set_option(ctx.OPT_WINDOWS, w)
+        for w in (1, 0):  # 2: windows from N = 2048 whatever an earlier autotune found
+            ctx.set_option(ctx.OPT_WINDOWS, 2 * w)
             got[w] = ctx.cmi_batch(batch).cpu().numpy()
     finally:
         ctx.set_option(ctx.OPT_WINDOWS, 1)
