@@ -140,6 +140,10 @@ typedef enum ksg_option {
                              * (FP64) hold at most this many elements: 0 (default) = 2^27, i.e.
                              * 1.5 GiB of workspace; smaller values bound the workspace (more
                              * launches, same results) */
+  KSG_OPT_XCOUNT_LAYOUT = 10, /* X counts of grouped problems: 0 = one query per lane (4
+                               * references per step); 1 = one query per wave, 64 references per
+                               * instruction, counts by mask population (same partial sums, bit
+                               * for bit) */
   KSG_OPT_MEM_LIMIT = 9,    /* bytes of device workspace the context may hold (columns pool,
                              * radii, terms, descriptors, graphs...): 0 (default) = no limit; a
                              * batch that needs more fails with KSG_ENOMEM and leaves the context
@@ -391,6 +395,13 @@ typedef struct ksg_select_opts {
   int32_t sequential; /* 1: sequential max-statistic test of the kept sources (after pruning;
                        * skipped when the omnibus test ran and was not significant) */
   int32_t max_cond;   /* 0 = the library's limit; else at most this many conditioning columns */
+  /* Resume (checkpoint of a run cut short): host int32 [n_resume] candidate indices
+   * (v*max_lag + lag-1) included by an earlier run of the same target, data, permutations and
+   * options, in inclusion order.  They start the conditioning set, leave the pool and head the
+   * parent list (cmi and pval NaN: their tests are not re-run); n_steps counts the new tests
+   * only.  Multivariate modes only.  n_resume = 0: a fresh selection. */
+  const int32_t* resume;
+  int32_t n_resume;
 } ksg_select_opts;
 
 enum { KSG_MODE_MULTIVARIATE_TE = 0, KSG_MODE_BIVARIATE_TE = 1, KSG_MODE_MULTIVARIATE_MI = 2 };

@@ -79,6 +79,8 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
     return c->fail(KSG_EINVAL, "select_parents: bad data shape");
   if (out->capacity < 0) return c->fail(KSG_EINVAL, "select_parents: negative capacity");
   if (o->max_cond < 0) return c->fail(KSG_EINVAL, "select_parents: max_cond must be >= 0");
+  if (o->n_resume < 0 || (o->n_resume > 0 && !o->resume) || (o->n_resume > 0 && o->mode == KSG_MODE_BIVARIATE_TE))
+    return c->fail(KSG_EINVAL, "select_parents: resume needs n_resume >= 0, a host array, and a multivariate mode");
   if (o->learned && !(o->margin_lo >= 0 && o->margin_hi >= 0))
     return c->fail(KSG_EINVAL, "select_parents: margins must be >= 0");
   if (o->mode < KSG_MODE_MULTIVARIATE_TE || o->mode > KSG_MODE_MULTIVARIATE_MI || (o->prune != 0 && o->prune != 1) ||
@@ -250,6 +252,18 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
   } else {
     for (int i = 0; i < s.C; ++i)
       if (o->mode == KSG_MODE_MULTIVARIATE_TE || i / s.L != target) s.pool.push_back(i);
+    // resume: the recorded inclusions of an earlier run come first, without their tests
+    for (int r = 0; r < o->n_resume; ++r) {
+      const auto it = std::find(s.pool.begin(), s.pool.end(), (int)o->resume[r]);
+      if (it == s.pool.end())
+        return c->fail(KSG_EINVAL, "select_parents: resume[%d] = %d is not an unselected candidate of this mode", r,
+                       o->resume[r]);
+      s.pool.erase(it);
+      s.selected.push_back(o->resume[r]);
+      incl.push_back(o->resume[r]);
+      incl_t.push_back(NAN);
+      incl_p.push_back(NAN);
+    }
     st = include_loop();
     if (st) return st;
   }

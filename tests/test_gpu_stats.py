@@ -257,3 +257,24 @@ def test_bench_configuration_sampled_parity(lib, ctx):
             xs = cand[pool[ci]] if p == 0 else cand[pool[ci]][perms[p - 1]]
             ref = ksg_cmi(xs, y, z, 4)
             assert abs(table[ci, p] - ref) <= tol(ref), (m, ci, p)
+
+
+def test_select_parents_resume_from_record(lib, ctx):
+    """A selection resumed from the first inclusions of an earlier run (its checkpoint) ends
+    with the same parents; its new steps are the oracle's greedy steps from that set."""
+    data = _small_chain(31)
+    L, P = 2, 19
+    cand, y = embed(data, target=3, max_lag=L)
+    perms = workloads.permutations(y.size, P, seed=32)
+    full = ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=L)
+    assert len(full["candidates"]) >= 2  # the case needs two inclusions
+    head = full["candidates"][:1]
+    r = ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=L, resume=head)
+    assert r["candidates"] == full["candidates"]
+    assert r["n_steps"] == full["n_steps"] - 1
+    assert np.isnan(r["cmi"][0]) and r["cmi"][1:] == full["cmi"][1:] and r["pval"][1:] == full["pval"][1:]
+    pool = [c for c in range(cand.shape[0]) if c not in head]
+    sel, steps = greedy_select(cand, y, 4, perms, alpha=0.05, pool=pool, selected=head)
+    assert sel == r["candidates"] and len(steps) == r["n_steps"]
+    with pytest.raises(lib.KsgError):
+        ctx.select_parents(dev(data), target=3, perms=dev(perms), k=4, max_lag=L, resume=[999])
