@@ -698,8 +698,6 @@ def main():
                     help="build the learned-null training set and save it (npz) instead of benchmarking")
     ap.add_argument("--no-selection", action="store_true",
                     help="skip the learned-vs-plain parent selection on the AR(2) network")
-    ap.add_argument("--xcount-layout", type=int, default=None, choices=[0, 1],
-                    help="grouped X count kernel: 0 one query per lane, 1 one query per wave")
     ap.add_argument("--no-graph", action="store_true",
                     help="skip the pass that replays the steps from HIP graphs")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -785,8 +783,6 @@ def main():
     ctx.set_option(ctx.OPT_GROUP_SIZE, args.group_size)
     ctx.set_option(ctx.OPT_ALGORITHM, args.algorithm)
     ctx.set_option(ctx.OPT_WINDOWS, 0 if args.no_windows else 1)
-    if args.xcount_layout is not None:
-        ctx.set_option(ctx.OPT_XCOUNT_LAYOUT, args.xcount_layout)
     tables = {m: torch.empty((25 - m, N_PERM + 1), dtype=torch.float64, device="cuda") for m in FORCED_M}
 
     def step():

@@ -140,10 +140,6 @@ typedef enum ksg_option {
                              * (FP64) hold at most this many elements: 0 (default) = 2^27, i.e.
                              * 1.5 GiB of workspace; smaller values bound the workspace (more
                              * launches, same results) */
-  KSG_OPT_XCOUNT_LAYOUT = 10, /* X counts of grouped problems: 0 = one query per lane (4
-                               * references per step); 1 = one query per wave, 64 references per
-                               * instruction, counts by mask population (same partial sums, bit
-                               * for bit) */
   KSG_OPT_MEM_LIMIT = 9,    /* bytes of device workspace the context may hold (columns pool,
                              * radii, terms, descriptors, graphs...): 0 (default) = no limit; a
                              * batch that needs more fails with KSG_ENOMEM and leaves the context

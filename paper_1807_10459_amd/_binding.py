@@ -241,7 +241,6 @@ class Context:
     OPT_GROUP_CHUNK = 7
     OPT_TILE_Q = 8
     OPT_MEM_LIMIT = 9
-    OPT_XCOUNT_LAYOUT = 10
 
     def __init__(self, device: int = 0, stream=None):
         import torch

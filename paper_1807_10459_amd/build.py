@@ -19,8 +19,6 @@ SOURCES = [  # longest compiles first, so that the parallel build ends early
     "ksg_search_kp17.hip",
     "ksg_window_alg2.hip",
     "ksg_search_wide.hip",
-    "ksg_xcount_t_g8.hip",
-    "ksg_xcount_t_g16.hip",
     "ksg_group_wide_kp5.hip",
     "ksg_group_wide_kp9.hip",
     "ksg_group_kp5_g8.hip",

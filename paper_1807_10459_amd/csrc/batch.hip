@@ -759,7 +759,7 @@ int ksg_ctx::enqueue_batch(const BatchPlan& P, const void* d_desc_v, const WorkI
                                        m, d_w, stream));
       if ((st = span_end(1, stream)) || (st = span_begin(stream))) return st;
       KSG_HIP(this, launch_ksg_group_xcount(pool_base, d_gdesc, d_items + c.item_off, (int)c.items.size(), d_e, d_t,
-                                            d_htab, d_part, m, G, d_w, stream, xcount_transposed));
+                                            d_htab, d_part, m, G, d_w, stream));
       if ((st = span_end(2, stream))) return st;
     }
     return KSG_OK;
@@ -831,7 +831,6 @@ static std::vector<uint64_t> batch_key(const ksg_ctx* c, const std::vector<Probl
   key.push_back((uint64_t)c->use_windows | ((uint64_t)c->windows_untuned << 1));
   key.push_back((uint64_t)c->group_chunk_elems);
   key.push_back((uint64_t)c->tile_q);
-  key.push_back((uint64_t)c->xcount_transposed);
   key.push_back((uint64_t)c->tuned);
   for (int t = 0; t < 2; ++t)
     for (int m = 0; m < 15; ++m) key.push_back((uint64_t)c->tuned_g[t][m]);

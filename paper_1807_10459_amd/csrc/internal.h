@@ -153,7 +153,7 @@ hipError_t launch_ksg_yzcount(const float* base, const YZDesc* d_ydesc, const Wo
 hipError_t launch_ksg_group_xcount(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
                                    int n_items, const float* E, const double* T, const double* d_htab,
                                    double* d_partials, int m, int G, unsigned long long* d_work,
-                                   hipStream_t stream, bool transposed = false);
+                                   hipStream_t stream);
 hipError_t launch_key_order(const GroupDesc* d_gdesc, int n_groups, int max_pad, float* base,
                             hipStream_t stream);
 hipError_t launch_interleave(const GroupDesc* d_gdesc, int n_groups, int max_pad, float* base,

@@ -275,10 +275,6 @@ extern "C" int ksg_ctx_set_option(ksg_ctx* c, int option, int64_t value) {
       c->use_graph = value != 0;
       if (!c->use_graph) c->clear_graphs();
       return KSG_OK;
-    case KSG_OPT_XCOUNT_LAYOUT:
-      if (value != 0 && value != 1) return c->fail(KSG_EINVAL, "X count layout must be 0 or 1");
-      c->xcount_transposed = value == 1;
-      return KSG_OK;
     case KSG_OPT_MEM_LIMIT:
       if (value < 0) return c->fail(KSG_EINVAL, "workspace limit must be >= 0 bytes (0 = none)");
       c->mem_limit = value;

@@ -27,8 +27,6 @@ extern const void* group_radius_kernels_kp5_g8_wide[16];
 extern const void* group_radius_kernels_kp9_g8_wide[16];
 extern const void* group_xcount_kernels_g8_wide[16];
 extern const void* search_kernels_wide[3];
-extern const void* group_xcount_t_kernels_g8[kGroupMaxM + 1];
-extern const void* group_xcount_t_kernels_g16[kGroupMaxM16 + 1];
 
 // ------------------------------------------------------------------ packing
 
@@ -361,15 +359,11 @@ hipError_t launch_ksg_yzcount(const float* base, const YZDesc* d_ydesc, const Wo
 hipError_t launch_ksg_group_xcount(const float* base, const GroupDesc* d_gdesc, const WorkItem* d_items,
                                    int n_items, const float* E, const double* T, const double* d_htab,
                                    double* d_partials, int m, int G, unsigned long long* d_work,
-                                   hipStream_t stream, bool transposed) {
+                                   hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
   if (m < 0 || m > kGroupMaxM || (G != 8 && G != 16) || (G == 16 && m > kGroupMaxM16)) return hipErrorInvalidValue;
-  const void* fn;
-  if (transposed)
-    fn = G == 8 ? group_xcount_t_kernels_g8[m] : group_xcount_t_kernels_g16[m];
-  else
-    fn = m > kGroupMaxM16 ? group_xcount_kernels_g8_wide[m - kGroupMaxM16 - 1]
-                          : (G == 8 ? group_xcount_kernels_g8 : group_xcount_kernels_g16)[m];
+  const void* fn = m > kGroupMaxM16 ? group_xcount_kernels_g8_wide[m - kGroupMaxM16 - 1]
+                                    : (G == 8 ? group_xcount_kernels_g8 : group_xcount_kernels_g16)[m];
   const float* a0 = base;
   const GroupDesc* a1 = d_gdesc;
   const WorkItem* a2 = d_items;

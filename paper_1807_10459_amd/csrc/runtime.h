@@ -135,7 +135,6 @@ struct ksg_ctx {
   int tuned_win_n[ksg::kMaxDimsCompiled + 1] = {0};  // [D]: smallest N searched with windows
   bool tuned = false;
   int tile_q = 0;                // KSG_OPT_TILE_Q: 0 = tuned (256 before tuning), or 64/128/256
-  bool xcount_transposed = false;  // KSG_OPT_XCOUNT_LAYOUT: X counts with one query per wave
   bool use_graph = false;        // KSG_OPT_USE_GRAPH: capture batches into HIP graphs and replay them
   int64_t group_chunk_elems = 0; // KSG_OPT_GROUP_CHUNK: 0 = kGroupChunkElems
 

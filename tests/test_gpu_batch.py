@@ -187,39 +187,3 @@ def test_workspace_limit_reports_enomem(lib):
         ref = ksg_cmi(x, p.y, p.z, 4)
         assert abs(got[idx] - ref) <= tol(ref), idx
 
-
-@pytest.mark.parametrize("m,G,kind", [(0, 8, "gaussian"), (1, 8, "gaussian"), (3, 16, "grid"), (8, 8, "gaussian"),
-                                      (14, 16, "gaussian"), (20, 8, "gaussian"), (30, 8, "unit12")])
-def test_xcount_layouts_bit_identical(lib, ctx, m, G, kind):
-    """The two layouts of the grouped X count kernel (one query per lane, one query per wave)
-    give the same partial sums bit for bit, hence the same estimates, and the oracle's."""
-    import torch
-    g = workloads.rng(2100 + m)
-    n, n_cand, n_perm = 1100 + 37 * m, 3, 6  # ragged tiles and 64-row blocks
-    p = workloads.random_problem(2200 + m, n, 1, 1, m, 4, kind=kind)
-    if kind == "grid":
-        cands = g.integers(0, 4, size=(n_cand, n)).astype(np.float32)
-    else:
-        cands = g.standard_normal((n_cand, n)).astype(np.float32)
-    cands[0] = (cands[0] + p.y[:, 0]).astype(np.float32)
-    perms = workloads.permutations(n, n_perm, seed=2300 + m)
-    y, z, dc, dp = soa(p.y), soa(p.z), dev(cands), dev(perms)
-    probs = [lib.Problem(dc[c], y, z, 4, perm_x=None if q == 0 else dp[q - 1])
-             for c in range(n_cand) for q in range(n_perm + 1)]
-    out = {}
-    ctx.set_option(ctx.OPT_GROUP_SIZE, G)
-    try:
-        for layout in (0, 1):
-            ctx.set_option(ctx.OPT_XCOUNT_LAYOUT, layout)
-            out[layout] = ctx.cmi_batch(probs).cpu().numpy()
-    finally:
-        ctx.set_option(ctx.OPT_XCOUNT_LAYOUT, 0)
-        ctx.set_option(ctx.OPT_GROUP_SIZE, -1)
-    torch.cuda.synchronize()
-    assert np.array_equal(out[0], out[1]), np.max(np.abs(out[0] - out[1]))
-    zz = p.z if m > 0 else None
-    for idx in (0, 1, len(probs) - 1):
-        c, q = divmod(idx, n_perm + 1)
-        x = cands[c] if q == 0 else cands[c][perms[q - 1]]
-        ref = ksg_cmi(x, p.y, zz, 4)
-        assert abs(out[1][idx] - ref) <= tol(ref), idx
