@@ -297,7 +297,9 @@ def c4_evaluate(ctx, args, log):
     net, hist = train_threshold_net(ctx, feats[tr].contiguous(), targ[tr].contiguous(),
                                     workloads.mlp_init(4243), epochs=60, batch=512, lr=2e-3)
     t_train = time.perf_counter() - t1
-    hi_idx = torch.nonzero(held).flatten()
+    # margins from the held-out networks of the evaluation's size class (N >= 14,000: 5 and 10
+    # trials; feature 0 is log N): the gate's errors grow with N and with the step's depth
+    hi_idx = torch.nonzero(held & (feats[:, 0] >= float(np.log(14000.0)))).flatten()
     cal = calibrate(net, feats[hi_idx].contiguous(), obs[hi_idx].contiguous(), rate=0.0025)
     log(f"dataset {feats.shape[0]} examples in {t_data:.1f} s; training {t_train:.1f} s "
         f"(loss {hist[0]:.4f} -> {hist[-1]:.4f}); calibration {cal}")
@@ -319,7 +321,8 @@ def c4_evaluate(ctx, args, log):
         for t in targets:
             kw = dict(k=K, max_lag=MAX_LAG, alpha=0.05, omnibus=True)
             if mode != "plain":
-                kw.update(learned=net, margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"], judge=mode == "judged")
+                kw.update(learned=net, margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"], judge=mode == "judged",
+                          verify_stop=True)
             out[t] = ctx.select_parents(data, t, perms, **kw)
             log(f"{mode} target {t}: parents {out[t]['parents']} steps {out[t]['n_steps']} "
                 f"truncated {out[t]['truncated']} fallback {out[t]['n_fallback']} disagree {out[t]['n_disagree']} "

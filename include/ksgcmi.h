@@ -398,6 +398,9 @@ typedef struct ksg_select_opts {
    * only.  Multivariate modes only.  n_resume = 0: a fresh selection. */
   const int32_t* resume;
   int32_t n_resume;
+  int32_t verify_stop; /* learned null: 1 = a step the gate would stop on runs the plain test,
+                        * whose decision is taken (a wrong stop loses every later parent, a wrong
+                        * inclusion adds one); 0 = the gate decides both ways */
 } ksg_select_opts;
 
 enum { KSG_MODE_MULTIVARIATE_TE = 0, KSG_MODE_BIVARIATE_TE = 1, KSG_MODE_MULTIVARIATE_MI = 2 };

@@ -54,7 +54,7 @@ class _SelectOpts(C.Structure):
                 ("learned", C.c_void_p), ("margin_lo", C.c_double), ("margin_hi", C.c_double),
                 ("judge", C.c_int32), ("max_steps", C.c_int32), ("mode", C.c_int32), ("prune", C.c_int32),
                 ("sequential", C.c_int32), ("max_cond", C.c_int32), ("resume", C.c_void_p),
-                ("n_resume", C.c_int32)]
+                ("n_resume", C.c_int32), ("verify_stop", C.c_int32)]
 
 
 class _ParentSet(C.Structure):
@@ -392,12 +392,13 @@ class Context:
                        margin_lo: float = 1.0, margin_hi: float = 1.0, judge: bool = False,
                        max_steps: int = 0, capacity: int = 64, mode: str = "mte",
                        prune: bool = False, sequential: bool = False, max_cond: int = 0,
-                       resume: Sequence[int] = ()) -> dict:
+                       resume: Sequence[int] = (), verify_stop: bool = False) -> dict:
         """Parents of one target.  mode: "mte" (multivariate TE), "bte" (bivariate TE) or "mmi"
         (multivariate MI); prune: min-statistic pruning of the selected sources; sequential:
         sequential max-statistic test of the kept sources; max_cond: conditioning columns allowed
         (0 = the library's limit); "truncated" in the result reports a selection that ended at it;
-        resume: candidate indices an earlier run included (in order), to continue from them."""
+        resume: candidate indices an earlier run included (in order), to continue from them;
+        verify_stop: with a learned null, a step the gate would stop on runs the plain test."""
         import torch
         _check_dtype(data, torch.float32, "data")
         _check_dtype(perms, torch.int32, "perms")
@@ -406,6 +407,7 @@ class Context:
                            _ptr(perms), learned._h if learned is not None else None, float(margin_lo),
                            float(margin_hi), int(bool(judge)), int(max_steps), MODES[mode], int(bool(prune)),
                            int(bool(sequential)), int(max_cond))
+        opts.verify_stop = int(bool(verify_stop))
         res_arr = np.ascontiguousarray(np.asarray(list(resume), dtype=np.int32))
         if res_arr.size:
             opts.resume, opts.n_resume = res_arr.ctypes.data, int(res_arr.size)

@@ -34,6 +34,7 @@ SOURCES = [  # longest compiles first, so that the parallel build ends early
     "mlp_kernels.hip",
     "mlp_api.hip",
     "autotune.hip",
+    "host_stats.cpp",
 ]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

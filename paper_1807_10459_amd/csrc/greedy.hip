@@ -186,11 +186,12 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
                        o->margin_lo, o->margin_hi, &verdict, &c_star, &t_obs, pred);
       if (st) return st;
       gate_verdict = verdict;
-      if (verdict != 0) {
+      if (verdict > 0 || (verdict < 0 && !o->verify_stop)) {
         decision = verdict > 0 ? 1 : 0;
         run_full = o->judge != 0;
         if (!o->judge) out->n_gate_decided++;
       } else {
+        // borderline, or a predicted stop that the plain test confirms (verify_stop)
         out->n_fallback++;
       }
     }
@@ -486,49 +487,5 @@ extern "C" int ksg_greedy_step(ksg_ctx* c, const float* cand, const float* y, in
   result->pval = m.pval;
   result->tau05 = m.tau05;
   result->tau01 = m.tau01;
-  return KSG_OK;
-}
-
-extern "C" int ksg_fdr_bh(const double* pvals, int32_t n, double alpha, int32_t* reject) {
-  if (!pvals || !reject || n < 0 || !(alpha > 0 && alpha < 1)) return KSG_EINVAL;
-  std::vector<int> order(n);
-  for (int i = 0; i < n; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pvals[a] < pvals[b]; });
-  int r = 0;
-  for (int i = 0; i < n; ++i)
-    if (pvals[order[i]] <= (double)(i + 1) * alpha / n) r = i + 1;
-  for (int i = 0; i < n; ++i) reject[i] = 0;
-  for (int i = 0; i < r; ++i) reject[order[i]] = 1;
-  return KSG_OK;
-}
-
-extern "C" int ksg_maxstat_sequential(const double* table, int32_t rows, int32_t n_perm, double alpha,
-                                      int32_t* significant, double* pval) {
-  if (!table || !significant || !pval || rows < 0 || n_perm < 1 || !(alpha > 0 && alpha < 1)) return KSG_EINVAL;
-  const int64_t W = (int64_t)n_perm + 1;
-  std::vector<int> rank(rows);
-  for (int i = 0; i < rows; ++i) rank[i] = i;
-  // descending originals, the lower row first on ties
-  std::stable_sort(rank.begin(), rank.end(), [&](int a, int b) { return table[a * W] > table[b * W]; });
-  // every round's surrogate values in descending order: sorted[r][p] = r-th largest of round p
-  std::vector<double> sorted((size_t)rows * n_perm), col(rows);
-  for (int p = 0; p < n_perm; ++p) {
-    for (int i = 0; i < rows; ++i) col[i] = table[i * W + 1 + p];
-    std::sort(col.begin(), col.end(), std::greater<double>());
-    for (int r = 0; r < rows; ++r) sorted[(size_t)r * n_perm + p] = col[r];
-  }
-  for (int i = 0; i < rows; ++i) {
-    significant[i] = 0;
-    pval[i] = 1.0;
-  }
-  for (int r = 0; r < rows; ++r) {
-    const int i = rank[r];
-    const double t = table[i * W];
-    int count = 0;
-    for (int p = 0; p < n_perm; ++p) count += sorted[(size_t)r * n_perm + p] >= t;
-    pval[i] = (double)count / n_perm;
-    if (!(pval[i] < alpha)) break;
-    significant[i] = 1;
-  }
   return KSG_OK;
 }

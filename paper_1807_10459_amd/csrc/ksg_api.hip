@@ -101,26 +101,6 @@ int ksg_ctx::wait_staging() {
   return KSG_OK;
 }
 
-// Harmonic numbers H_0..H_nmax in FP64 from a double-double running sum of 1/m (the
-// remainder of each reciprocal comes from an exact fused multiply-add), rounded once.
-void ksg_build_harmonic(int64_t nmax, double* out) {
-  double hi = 0.0, lo = 0.0;
-  out[0] = 0.0;
-  for (int64_t m = 1; m <= nmax; ++m) {
-    const double dm = (double)m;
-    const double r = 1.0 / dm;
-    const double e = std::fma(-r, dm, 1.0) / dm;  // 1/m = r + e (to ~2^-106 relative)
-    // (hi, lo) += (r, e): two-sum of the leading parts, then renormalise.
-    const double s = hi + r;
-    const double bb = s - hi;
-    const double err = (hi - (s - bb)) + (r - bb);
-    const double t = err + lo + e;
-    hi = s + t;
-    lo = t - (hi - s);
-    out[m] = hi;
-  }
-}
-
 int ksg_ctx::ensure_htab(int64_t n) {
   if (htab_n >= n) return KSG_OK;
   int64_t want = std::max<int64_t>(std::max<int64_t>(n, 2 * htab_n), 65536);
@@ -187,11 +167,6 @@ extern "C" int ksg_device_props_get(int32_t device, ksg_device_props* out) {
   return KSG_OK;
 }
 
-extern "C" int ksg_harmonic_table(int64_t nmax, double* out) {
-  if (nmax < 0 || !out) return KSG_EINVAL;
-  ksg_build_harmonic(nmax, out);
-  return KSG_OK;
-}
 
 extern "C" int ksg_ctx_create(ksg_ctx** out, int device, void* hip_stream) {
   if (!out) return KSG_EINVAL;
