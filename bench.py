@@ -32,12 +32,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_VALU = 157.3e12 / 2  # FP32 lane-operations per second that are not FMAs
-# Lane-operations per second of the 4-cycle VALU instruction classes (maxima, minima, compares,
-# add-with-carry, any instruction with an SGPR operand): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-# Reported beside the roofline as a second denominator; it is not an upper bound on the
-# algorithmic rate (v_max3_f32 does two maxima per lane in one such instruction).
-PEAK_VALU_4CYCLE = 256 * 4 * 16 * 2.4e9
+# VALU lane-instructions per second of the part: 256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz (the
+# 157.3 TFLOP/s FP32 vector figure counts an FMA as two operations)
+PEAK_VALU = 157.3e12 / 2
 N_PERM = 200
 MAX_LAG = 5
 K = 4
@@ -447,7 +444,15 @@ def omnibus_bench(ksg, args):
     ctx.set_option(ctx.OPT_TIMING, 0)
     ms, ops, nl = kern["single"]
     D = len(src) + 1 + len(tgt)
-    achieved = ops / (ms * 1e-3)
+    # VALU lane-instructions per launch from the committed counter record of this launch (the
+    # window search at D = 16 under algorithm 1), over this run's mean launch time
+    rec_key = ("alg2" if args.algorithm == 2 else "single") if args.no_windows else \
+        ("window_alg2" if args.algorithm == 2 else "window")
+    valu_instr = _counter_record("valu_wave_instructions_per_launch", rec_key, OMNIBUS_RECORD, OMNIBUS_SOURCES)
+    t_launch = ms / nl * 1e-3
+    achieved = None if valu_instr is None else valu_instr * 64 / t_launch
+    pairs = N * (N - 1)
+    brute = (P + 1) * pairs * (4 * D + 2)
     res = out.cpu().numpy()
     line = {
         "metric": "CMI estimates/sec incl. surrogates (omnibus test, N=29950, k=4)"
@@ -467,14 +472,19 @@ def omnibus_bench(ksg, args):
         "config": {"workload": f"omnibus test of target 0's parent set, 20-node logistic network, "
                                f"N={N}, {len(src)} source + 1 target + {len(tgt)} target-past columns "
                                f"(D={D}), k=4, {P} surrogates"},
-        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 3),
-                     "peak": round(PEAK_VALU / 1e12, 3), "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_VALU, 4), "traffic": None,
-                     "frac_4cycle_class": round(achieved / PEAK_VALU_4CYCLE, 4),
-                     "kernel": KERNEL_NAMES[("alg2" if args.algorithm == 2 else "single") if args.no_windows
-                                            else ("window_alg2" if args.algorithm == 2 else "window")],
-                     "kernel_ms_per_launch": round(ms / nl, 3),
-                     "launches": nl, "ops_per_launch": ops / nl},
+        "roofline": {"bound": "alu", "achieved": None if achieved is None else round(achieved / 1e12, 3),
+                     "peak": round(PEAK_VALU / 1e12, 3), "unit": "T VALU lane-instructions/s",
+                     "frac": None if achieved is None else round(achieved / PEAK_VALU, 4), "traffic": None,
+                     "kernel": KERNEL_NAMES[rec_key],
+                     "kernel_ms_per_launch": round(ms / nl, 3), "launches": nl,
+                     "valu_wave_instructions_per_launch": valu_instr,
+                     "how": "achieved = SQ_INSTS_VALU per launch (committed rocprofv3 counter record) x 64 "
+                            "lanes / this run's mean launch time (HIP events)",
+                     # the kernel's own count of the operations over the pairs it visits, and the
+                     # method's brute-force count (N(N-1)(4D+2) per problem), each over the launch time
+                     "executed_ops_per_launch": ops / nl,
+                     "executed_ops_rate": round(ops / (ms * 1e-3) / 1e12, 3),
+                     "effective_ops_rate": round(brute / t_launch / 1e12, 3)},
         "omnibus_cmi": float(res[0]),
         "omnibus_pval": float(np.mean(res[1:] >= res[0])),
     }
@@ -494,6 +504,8 @@ def omnibus_bench(ksg, args):
 
 
 TRAFFIC_SOURCES = ("ksg_group.inc.h", "ksg_search.inc.h", "ksg_yzcount.hip")
+OMNIBUS_RECORD = "omnibus_window_kernel_counters.json"
+OMNIBUS_SOURCES = ("ksg_window.inc.h", "ksg_search.inc.h", "ksg_window.hip")
 KERNEL_NAMES = {"radius": "ksg_group_radius_kernel (k-NN radius of each problem of a group, "
                           "Y/Z distances shared, key-ordered windows)",
                 "yz_count": "ksg_yzcount_kernel (n_YZ and n_Z of every problem of a step at once: "
@@ -656,19 +668,20 @@ def uneven_bench(ksg, args):
     return line
 
 
-def _kernel_source_hash():
+def _kernel_source_hash(sources=None):
     import hashlib
     return hashlib.sha256(b"".join(open(os.path.join(ROOT, "paper_1807_10459_amd", "csrc", f), "rb").read()
-                                   for f in TRAFFIC_SOURCES)).hexdigest()
+                                   for f in (sources or TRAFFIC_SOURCES))).hexdigest()
 
 
-def _counter_record(field, kernel):
-    """A per-launch figure of a kernel from the committed counter record (HBM bytes, VALU
-    wave-instructions), or None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "ksg_group_kernels_traffic.json")
+def _counter_record(field, kernel, record="ksg_group_kernels_traffic.json", sources=None):
+    """A per-launch figure of a kernel from a committed counter record under profiles/ (HBM
+    bytes, VALU wave-instructions), or None when the kernel sources changed since the counters
+    were taken."""
+    path = os.path.join(ROOT, "profiles", record)
     try:
         rec = json.load(open(path))
-        if _kernel_source_hash() == rec["kernel_source_sha256"]:
+        if _kernel_source_hash(sources) == rec["kernel_source_sha256"]:
             return rec[field].get(kernel)
     except (OSError, KeyError, ValueError, AttributeError):
         pass
