@@ -297,7 +297,8 @@ def c4_evaluate(ctx, args, log):
     # margins from the held-out networks of the evaluation's size class (N >= 14,000: 5 and 10
     # trials; feature 0 is log N): the gate's errors grow with N and with the step's depth
     hi_idx = torch.nonzero(held & (feats[:, 0] >= float(np.log(14000.0)))).flatten()
-    cal = calibrate(net, feats[hi_idx].contiguous(), obs[hi_idx].contiguous(), rate=0.0025)
+    cal = calibrate(net, feats[hi_idx].contiguous(), obs[hi_idx].contiguous(), rate=0.0025,
+                    include_rate=args.include_rate)
     log(f"dataset {feats.shape[0]} examples in {t_data:.1f} s; training {t_train:.1f} s "
         f"(loss {hist[0]:.4f} -> {hist[-1]:.4f}); calibration {cal}")
 
@@ -310,7 +311,16 @@ def c4_evaluate(ctx, args, log):
     # plain: the permutation test on every step, no network; learned: the gate first, the
     # surrogates only for borderline steps; judged (--judge): the gate and the plain test on every
     # step, the plain decision taken (per-step agreement of the gate, not timed against)
-    modes = ("plain", "learned") + (("judged",) if args.judge else ())
+    modes = (() if args.plain_json else ("plain",)) + ("learned",) + (("judged",) if args.judge else ())
+    if args.plain_json:
+        # plain results of earlier runs of this workload (the plain path is deterministic: same
+        # network, permutations and options); their targets together must be the requested ones
+        recs = [json.loads(open(f).read().strip().splitlines()[-1]) for f in args.plain_json]
+        got = sorted(t for r in recs for t in r["targets"])
+        if got != sorted(targets):
+            raise SystemExit(f"--plain-json covers targets {got}, not the requested {sorted(targets)}")
+        plain_rec = {int(t): {"parents": [tuple(p) for p in ps]} for r in recs for t, ps in r["parents_plain"].items()}
+        res["plain"] = (plain_rec, sum(r["plain_seconds"] for r in recs))
     for mode in modes:
         torch.cuda.synchronize()
         tm = time.perf_counter()
@@ -331,7 +341,9 @@ def c4_evaluate(ctx, args, log):
 
     def sources(r, t):  # final parent variables (omnibus-gated sources + target past)
         vs = {v for (v, _) in r["parents"] if v == t}
-        if r["omnibus_tested"] and r["omnibus_significant"]:
+        # a plain record read from an earlier line holds the final parent list only (the
+        # omnibus test, which both runs apply to their own parent sets, gated it there)
+        if "omnibus_tested" not in r or (r["omnibus_tested"] and r["omnibus_significant"]):
             vs |= {v for (v, _) in r["parents"] if v != t}
         return vs
     n_vars = 20
@@ -344,7 +356,7 @@ def c4_evaluate(ctx, args, log):
     # conditioning sets agree), the learned run's decision (the gate's, or the surrogates' on a
     # borderline step) against the plain run's
     steps_compared, steps_agree = 0, 0
-    for t in targets:
+    for t in (targets if not args.plain_json else ()):
         pp, ll = plain[t], learned[t]
         for i in range(min(len(pp["steps"]), len(ll["steps"]))):
             if pp["candidates"][:i] != ll["candidates"][:i]:
@@ -360,7 +372,7 @@ def c4_evaluate(ctx, args, log):
     # ablation: the same gate driven by a per-(N, c) bucket mean-threshold table, evaluated on
     # the plain run's judged steps (pool size c = 100 - step in the multivariate-TE pool)
     eval_steps = [(N, n_vars * MAX_LAG - i, st["t_obs"], st["plain"])
-                  for r in plain.values() for i, st in enumerate(r["steps"]) if st["plain"] in (0, 1)]
+                  for r in plain.values() for i, st in enumerate(r.get("steps", ())) if st["plain"] in (0, 1)]
     ablation = bucket_table_ablation(feats[tr].cpu().numpy(), targ[tr].cpu().numpy(),
                                      feats[hi_idx].cpu().numpy(), obs[hi_idx].cpu().numpy(), 0.0025, eval_steps)
     ablation["network_held_out_fallback"] = round(cal["fallback"], 4)
@@ -378,17 +390,22 @@ def c4_evaluate(ctx, args, log):
         "learned_seconds": round(t_learned, 2),
         "pair_agreement": agree_pairs / (len(targets) * n_vars),
         "exact_parent_set_rate": exact / len(targets),
-        "step_agreement_common_path": steps_agree / max(steps_compared, 1),
+        "step_agreement_common_path": steps_agree / steps_compared if steps_compared else None,
         "steps_compared": steps_compared,
         "judged_step_agreement": (1.0 - disagree / max(steps_judged, 1)) if "judged" in res else None,
-        "truncated_targets_plain": sum(int(r["truncated"]) for r in plain.values()),
+        "truncated_targets_plain": (sum(int(r["truncated"]) for r in plain.values()) if not args.plain_json
+                                    else sum(r["truncated_targets_plain"] for r in recs)),
+        "plain_from": args.plain_json,
+        "include_rate": args.include_rate,
+        "omnibus": {str(t): [r["omnibus_tested"], r["omnibus_significant"]] for t, r in learned.items()},
         "truncated_targets_learned": sum(int(r["truncated"]) for r in learned.values()),
         "parents_plain": {str(t): r["parents"] for t, r in plain.items()},
         "parents_learned": {str(t): r["parents"] for t, r in learned.items()},
         "learned_fallback_steps": sum(r["n_fallback"] for r in learned.values()),
         "learned_gate_steps": sum(r["n_gate_decided"] for r in learned.values()),
         "learned_cmi": sum(r["n_cmi"] for r in learned.values()),
-        "plain_cmi": sum(r["n_cmi"] for r in plain.values()),
+        "plain_cmi": (sum(r["n_cmi"] for r in plain.values()) if not args.plain_json
+                      else sum(r["plain_cmi"] for r in recs)),
         "calibration": cal,
         "training": {"examples": int(feats.shape[0]), "held_out": int(hi_idx.numel()),
                      "dataset_s": round(t_data, 1), "train_s": round(t_train, 1),
@@ -708,6 +725,12 @@ def main():
                     help="ar2: CMI/s on the AR(2) forced path (default); c4: learned vs plain null")
     ap.add_argument("--targets", default=None, help="c4: comma-separated targets (default all 20)")
     ap.add_argument("--dataset", default=None, help="c4: load the training set from this npz")
+    ap.add_argument("--include-rate", type=float, default=None,
+                    help="c4: calibrate the gate with this allowance of wrong inclusions (and rate/2 of wrong "
+                         "stops) instead of rate/2 on both sides")
+    ap.add_argument("--plain-json", nargs="+", default=None,
+                    help="c4: skip the plain run and compare with the plain results of earlier c4 lines "
+                         "(their targets together must be the requested ones)")
     ap.add_argument("--judge", action="store_true",
                     help="c4: also run the judged selection (gate and plain test on every step)")
     ap.add_argument("--dump-dataset", default=None,

@@ -550,6 +550,17 @@ int ksg_gate_calibrate(ksg_ctx* ctx, const ksg_mlp* m, const float* feats, const
                        int64_t B, double rate, double* margin_lo, double* margin_hi,
                        double* fallback, int64_t* wrong);
 
+/* The same calibration with a separate allowance per side: margin_lo leaves at most
+ * floor(rate_stop * B) significant examples decided as stops, margin_hi at most
+ * floor(rate_include * B) non-significant examples decided as inclusions
+ * (ksg_gate_calibrate(rate) = this with rate/2 on both sides).  A wrong inclusion at the step
+ * where the plain test would stop lets the selection run on, so a caller that confirms every
+ * predicted stop with the surrogates (verify_stop) may want rate_include < rate_stop.  Both
+ * rates in [0, 1); outputs as above.  Synchronises. */
+int ksg_gate_calibrate_sides(ksg_ctx* ctx, const ksg_mlp* m, const float* feats, const double* obs,
+                             int64_t B, double rate_stop, double rate_include, double* margin_lo,
+                             double* margin_hi, double* fallback, int64_t* wrong);
+
 #ifdef __cplusplus
 }
 #endif

@@ -114,6 +114,8 @@ def _load():
         "ksg_mlp_fit_norm": ([vp, vp, vp, i64], i32),
         "ksg_gate_calibrate": ([vp, vp, vp, vp, i64, d, C.POINTER(d), C.POINTER(d), C.POINTER(d),
                                 C.POINTER(i64)], i32),
+        "ksg_gate_calibrate_sides": ([vp, vp, vp, vp, i64, d, d, C.POINTER(d), C.POINTER(d), C.POINTER(d),
+                                      C.POINTER(i64)], i32),
         "ksg_step_features": ([vp, vp, i32, vp, vp, i64, vp, i32, i32, i32, i32, i32, vp], i32),
         "ksg_fdr_bh": ([vp, i32, d, vp], i32),
         "ksg_maxstat_sequential": ([vp, i32, i32, d, vp, vp], i32),
@@ -541,11 +543,19 @@ class ThresholdNet:
     def fit_norm(self, feats):
         self.ctx._check(lib.ksg_mlp_fit_norm(self.ctx._h, self._h, _ptr(feats), feats.shape[0]), "ksg_mlp_fit_norm")
 
-    def calibrate(self, feats, obs, rate: float = 0.0025) -> dict:
+    def calibrate(self, feats, obs, rate: float = 0.0025, include_rate: float | None = None) -> dict:
+        """Gate margins (ksg_gate_calibrate); with include_rate, ksg_gate_calibrate_sides with
+        rate/2 for wrong stops and include_rate for wrong inclusions."""
         lo, hi, fb, wrong = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
-        self.ctx._check(lib.ksg_gate_calibrate(self.ctx._h, self._h, _ptr(feats), _ptr(obs), feats.shape[0],
-                                               float(rate), C.byref(lo), C.byref(hi), C.byref(fb), C.byref(wrong)),
-                        "ksg_gate_calibrate")
+        if include_rate is None:
+            self.ctx._check(lib.ksg_gate_calibrate(self.ctx._h, self._h, _ptr(feats), _ptr(obs), feats.shape[0],
+                                                   float(rate), C.byref(lo), C.byref(hi), C.byref(fb),
+                                                   C.byref(wrong)), "ksg_gate_calibrate")
+        else:
+            self.ctx._check(lib.ksg_gate_calibrate_sides(self.ctx._h, self._h, _ptr(feats), _ptr(obs),
+                                                         feats.shape[0], float(rate) / 2, float(include_rate),
+                                                         C.byref(lo), C.byref(hi), C.byref(fb), C.byref(wrong)),
+                            "ksg_gate_calibrate_sides")
         return dict(margin_lo=lo.value, margin_hi=hi.value, fallback=fb.value, wrong=wrong.value)
 
     def forward(self, feats):

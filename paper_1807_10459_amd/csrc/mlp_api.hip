@@ -383,11 +383,12 @@ extern "C" int ksg_mlp_fit_norm(ksg_ctx* c, ksg_mlp* m, const float* feats, int6
 // pred_0.05) / s, the gate includes when u > margin_hi and stops when u < -margin_lo.  Each
 // margin is the smallest value >= 0 for which at most floor(rate/2 * B) examples are decided
 // against their plain-test outcome on that side.
-extern "C" int ksg_gate_calibrate(ksg_ctx* c, const ksg_mlp* m, const float* feats, const double* obs,
-                                  int64_t B, double rate, double* margin_lo, double* margin_hi,
-                                  double* fallback, int64_t* wrong) {
+extern "C" int ksg_gate_calibrate_sides(ksg_ctx* c, const ksg_mlp* m, const float* feats, const double* obs,
+                                        int64_t B, double rate_stop, double rate_include, double* margin_lo,
+                                        double* margin_hi, double* fallback, int64_t* wrong) {
   if (!c) return KSG_EINVAL;
-  if (!m || !feats || !obs || B < 1 || !(rate >= 0 && rate < 1) || !margin_lo || !margin_hi || !fallback || !wrong)
+  if (!m || !feats || !obs || B < 1 || !(rate_stop >= 0 && rate_stop < 1) ||
+      !(rate_include >= 0 && rate_include < 1) || !margin_lo || !margin_hi || !fallback || !wrong)
     return c->fail(KSG_EINVAL, "ksg_gate_calibrate: bad argument");
   KSG_HIP(c, hipSetDevice(c->device));
   int st = c->reserve(c->tmp, sizeof(float) * 2 * (size_t)B, "predictions");
@@ -405,15 +406,16 @@ extern "C" int ksg_gate_calibrate(ksg_ctx* c, const ksg_mlp* m, const float* fea
     u[i] = (ob[2 * i] - (double)pred[2 * i]) / s;
     (ob[2 * i + 1] > 0.5 ? u_pos : u_neg).push_back(u[i]);
   }
-  const int64_t allow = (int64_t)std::floor(rate / 2.0 * (double)B);
-  // margin_hi: at most `allow` non-significant examples with u > margin_hi
+  const int64_t allow_hi = (int64_t)std::floor(rate_include * (double)B);
+  const int64_t allow_lo = (int64_t)std::floor(rate_stop * (double)B);
+  // margin_hi: at most `allow_hi` non-significant examples with u > margin_hi
   std::sort(u_neg.begin(), u_neg.end(), std::greater<double>());
   double hi = 0.0;
-  if ((int64_t)u_neg.size() > allow) hi = std::max(0.0, u_neg[allow]);
-  // margin_lo: at most `allow` significant examples with u < -margin_lo
+  if ((int64_t)u_neg.size() > allow_hi) hi = std::max(0.0, u_neg[allow_hi]);
+  // margin_lo: at most `allow_lo` significant examples with u < -margin_lo
   std::sort(u_pos.begin(), u_pos.end());
   double lo = 0.0;
-  if ((int64_t)u_pos.size() > allow) lo = std::max(0.0, -u_pos[allow]);
+  if ((int64_t)u_pos.size() > allow_lo) lo = std::max(0.0, -u_pos[allow_lo]);
   int64_t band = 0, bad = 0;
   for (int64_t i = 0; i < B; ++i) {
     const bool sig = ob[2 * i + 1] > 0.5;
@@ -426,4 +428,13 @@ extern "C" int ksg_gate_calibrate(ksg_ctx* c, const ksg_mlp* m, const float* fea
   *fallback = (double)band / (double)B;
   *wrong = bad;
   return KSG_OK;
+}
+
+extern "C" int ksg_gate_calibrate(ksg_ctx* c, const ksg_mlp* m, const float* feats, const double* obs,
+                                  int64_t B, double rate, double* margin_lo, double* margin_hi,
+                                  double* fallback, int64_t* wrong) {
+  if (!c) return KSG_EINVAL;
+  if (!(rate >= 0 && rate < 1)) return c->fail(KSG_EINVAL, "ksg_gate_calibrate: bad argument");
+  return ksg_gate_calibrate_sides(c, m, feats, obs, B, rate / 2.0, rate / 2.0, margin_lo, margin_hi, fallback,
+                                  wrong);
 }

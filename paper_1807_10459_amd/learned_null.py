@@ -107,6 +107,8 @@ def train_threshold_net(ctx: Context, feats, targets, init_params, epochs: int =
     return net, [float(h) for h in hist]
 
 
-def calibrate(net: ThresholdNet, feats, obs, rate: float = 0.0025) -> dict:
-    """Gate margins on held-out examples so that at most rate of them are decided wrongly."""
-    return net.calibrate(feats, obs, rate)
+def calibrate(net: ThresholdNet, feats, obs, rate: float = 0.0025, include_rate: float | None = None) -> dict:
+    """Gate margins on held-out examples so that at most rate of them are decided wrongly
+    (rate/2 per side); with include_rate, at most rate/2 wrong stops and include_rate wrong
+    inclusions."""
+    return net.calibrate(feats, obs, rate, include_rate)

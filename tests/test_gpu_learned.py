@@ -73,15 +73,16 @@ def test_fit_norm_matches_numpy(lib, ctx):
     assert np.max(np.abs(out - ref)) <= 1e-4 * max(1.0, np.abs(ref).max())
 
 
-def _calib_ref(pred, obs, rate):
+def _calib_ref(pred, obs, rate, include_rate=None):
     s = np.maximum(np.abs(pred[:, 1] - pred[:, 0]), 1e-30)
     u = (obs[:, 0] - pred[:, 0]) / s
     sig = obs[:, 1] > 0.5
-    allow = int(np.floor(rate / 2 * len(u)))
+    allow_lo = int(np.floor(rate / 2 * len(u)))
+    allow_hi = allow_lo if include_rate is None else int(np.floor(include_rate * len(u)))
     un = np.sort(u[~sig])[::-1]
     up = np.sort(u[sig])
-    hi = max(0.0, un[allow]) if un.size > allow else 0.0
-    lo = max(0.0, -up[allow]) if up.size > allow else 0.0
+    hi = max(0.0, un[allow_hi]) if un.size > allow_hi else 0.0
+    lo = max(0.0, -up[allow_lo]) if up.size > allow_lo else 0.0
     return lo, hi
 
 
@@ -99,6 +100,30 @@ def test_calibration_matches_reference(lib, ctx):
     lo, hi = _calib_ref(pred, obs, 0.01)
     assert abs(r["margin_lo"] - lo) <= 1e-4 * max(1, lo) and abs(r["margin_hi"] - hi) <= 1e-4 * max(1, hi)
     assert r["wrong"] <= 2 * int(0.005 * B) + 2
+
+
+@pytest.mark.parametrize("include_rate", [0.0, 0.001, 0.02])
+def test_calibration_per_side_matches_reference(lib, ctx, include_rate):
+    g = workloads.rng(75)
+    B = 3000
+    p = workloads.mlp_init(6)
+    net = lib.ThresholdNet(ctx, p)
+    feats = g.standard_normal((B, 16)).astype(np.float32)
+    w = mlp.bf16_round(p).astype(np.float64)
+    pred, _ = mlp.forward(w, feats.astype(np.float64))
+    obs = np.stack([pred[:, 0] + g.standard_normal(B) * np.abs(pred[:, 1] - pred[:, 0]),
+                    (g.random(B) < 0.4).astype(np.float64)], 1)
+    r = net.calibrate(dev(feats), dev(obs), rate=0.01, include_rate=include_rate)
+    lo, hi = _calib_ref(pred, obs, 0.01, include_rate)
+    assert abs(r["margin_lo"] - lo) <= 1e-4 * max(1, lo) and abs(r["margin_hi"] - hi) <= 1e-4 * max(1, hi)
+    # wrong inclusions are bounded by the include allowance (ties at the margin aside)
+    s_ = np.maximum(np.abs(pred[:, 1] - pred[:, 0]), 1e-30)
+    u = (obs[:, 0] - pred[:, 0]) / s_
+    assert int(np.sum((u > r["margin_hi"] + 1e-4 * max(1, hi)) & (obs[:, 1] < 0.5))) <= int(include_rate * B)
+    # the symmetric form equals rate/2 on both sides
+    r2 = net.calibrate(dev(feats), dev(obs), rate=0.01, include_rate=0.005)
+    r3 = net.calibrate(dev(feats), dev(obs), rate=0.01)
+    assert r2["margin_lo"] == r3["margin_lo"] and r2["margin_hi"] == r3["margin_hi"]
 
 
 def _dataset(lib, ctx, seeds, P=500, n_sub=64, m_max=4, steps=3):
@@ -183,3 +208,28 @@ def test_learned_gate_gain_over_table_and_select_parents(lib, ctx):
     assert learned["n_gate_decided"] >= 1 and learned["n_cmi"] < plain["n_cmi"]
     if judged["n_disagree"] == 0:
         assert learned["parents"] == plain["parents"]
+
+
+def test_verify_stop_confirms_every_predicted_stop(lib, ctx):
+    """A gate that never includes (margin_hi huge) and stops whenever u < 0: with verify_stop
+    every predicted stop runs the plain test, so the selection is the plain one step for step
+    and no step is decided by the gate alone; without it the first predicted stop ends the
+    selection there."""
+    net = lib.ThresholdNet(ctx, workloads.mlp_init(21))
+    data = workloads.logistic_network(seed=998, n_trials=1, T=3000).data
+    perms = dev(workloads.permutations(2995, 200, seed=997))
+    kw = dict(k=4, max_lag=5, prune=False)
+    plain = ctx.select_parents(dev(data), 6, perms, **kw)
+    ver = ctx.select_parents(dev(data), 6, perms, learned=net, margin_lo=0.0, margin_hi=1e30, verify_stop=True, **kw)
+    assert ver["parents"] == plain["parents"] and ver["n_steps"] == plain["n_steps"]
+    assert ver["n_gate_decided"] == 0 and ver["n_fallback"] == ver["n_steps"]
+    verdicts = [st["verdict"] for st in ver["steps"]]
+    assert all(v in (-1, 0) for v in verdicts)
+    assert all(st["plain"] == pst["plain"] for st, pst in zip(ver["steps"], plain["steps"]))
+    raw = ctx.select_parents(dev(data), 6, perms, learned=net, margin_lo=0.0, margin_hi=1e30, **kw)
+    if -1 in verdicts:
+        first = verdicts.index(-1)
+        assert raw["n_steps"] == first + 1 and raw["n_gate_decided"] == 1
+        assert raw["parents"] == plain["parents"][:first]
+    else:
+        assert raw["parents"] == plain["parents"]
