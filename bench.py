@@ -823,9 +823,11 @@ def main():
     ctx.set_option(ctx.OPT_ALGORITHM, args.algorithm)
     ctx.set_option(ctx.OPT_WINDOWS, 0 if args.no_windows else 1)
     tables = {m: torch.empty((25 - m, N_PERM + 1), dtype=torch.float64, device="cuda") for m in FORCED_M}
+    # every step embeds again, into the same buffers (so a captured graph finds the same addresses)
+    emb = ctx.embed(data, target=0, max_lag=MAX_LAG)
 
     def step():
-        cand, y = ctx.embed(data, target=0, max_lag=MAX_LAG)
+        cand, y = ctx.embed(data, target=0, max_lag=MAX_LAG, out=emb)
         results = {}
         for m in FORCED_M:
             cond = order[:m]

@@ -360,13 +360,23 @@ class Context:
         return dict(c_star=r.c_star, count=r.count, significant=bool(r.significant), n_perm=r.n_perm,
                     t_obs=r.t_obs, pval=r.pval, tau05=r.tau05, tau01=r.tau01)
 
-    def embed(self, data, target: int, max_lag: int):
+    def embed(self, data, target: int, max_lag: int, out=None):
+        """Candidate columns [n_vars*max_lag][N] and target column [N]; out = (cand, y) to write
+        into caller-owned buffers (fixed addresses, e.g. for graph replay of later steps)."""
         import torch
         _check_dtype(data, torch.float32, "data")
         n_trials, n_vars, T = data.shape
         N = n_trials * (T - max_lag)
-        cand = torch.empty((n_vars * max_lag, N), dtype=torch.float32, device=data.device)
-        y = torch.empty(N, dtype=torch.float32, device=data.device)
+        if out is None:
+            cand = torch.empty((n_vars * max_lag, N), dtype=torch.float32, device=data.device)
+            y = torch.empty(N, dtype=torch.float32, device=data.device)
+        else:
+            cand, y = out
+            _check_dtype(cand, torch.float32, "cand")
+            _check_dtype(y, torch.float32, "y")
+            if tuple(cand.shape) != (n_vars * max_lag, N) or tuple(y.shape) != (N,) or not (
+                    cand.is_contiguous() and y.is_contiguous()):
+                raise ValueError(f"embed: out must be contiguous [{n_vars * max_lag}][{N}] and [{N}]")
         self._check(lib.ksg_embed(self._h, _ptr(data), n_vars, T, n_trials, int(target), int(max_lag),
                                   _ptr(cand), _ptr(y)), "ksg_embed")
         return cand, y

@@ -24,6 +24,16 @@ def test_embed_matches_oracle(lib, ctx):
     rc, ry = embed(net.data, target=2, max_lag=5)
     assert np.array_equal(cand.cpu().numpy(), rc)
     assert np.array_equal(y.cpu().numpy(), ry)
+    # into caller-owned buffers (reused: a second target overwrites every element)
+    import torch
+    out = (torch.full_like(cand, float("nan")), torch.full_like(y, float("nan")))
+    for tgt in (4, 2):
+        c2, y2 = ctx.embed(dev(net.data), target=tgt, max_lag=5, out=out)
+        assert c2.data_ptr() == out[0].data_ptr() and y2.data_ptr() == out[1].data_ptr()
+        rc, ry = embed(net.data, target=tgt, max_lag=5)
+        assert np.array_equal(c2.cpu().numpy(), rc) and np.array_equal(y2.cpu().numpy(), ry)
+    with pytest.raises(ValueError):
+        ctx.embed(dev(net.data), target=2, max_lag=4, out=out)
 
 
 @pytest.mark.parametrize("c,P", [(1, 1), (1, 200), (7, 19), (25, 200), (100, 500), (3, 4096)])
