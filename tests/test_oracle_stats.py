@@ -286,3 +286,70 @@ def test_sequential_final_test_removes_a_noise_source():
     kept, removed, pv, table = sequential_final_test(cand, y, [3, 0, 2], 3, L, 4, perms)
     assert removed == [2] and kept == [3, 0]
     assert pv[0] < 0.05 and pv[2] >= 0.05 and table.shape == (2, 40)
+
+
+def _var_exact_cmi(params, n_vars, L):
+    """Exact Gaussian I(x_c ; y | x_Z) on the AR(2) network's stationary process.
+
+    The generator is a VAR(3) in the n_vars-dim state (each node's own AR(2) terms plus the
+    target's three lagged drivers), unit-variance noise.  Its companion form over the lags
+    0..L gives s(t) = F s(t-1) + w(t), and the stationary covariance solves the discrete
+    Lyapunov equation S = F S F^T + Q.  Candidate (v, l) is x_v(t-l), index l*n + v of s(t);
+    Y is x_target(t), index target."""
+    from scipy.linalg import solve_discrete_lyapunov
+    n = n_vars
+    A = [np.zeros((n, n)) for _ in range(3)]
+    A[0][np.arange(n), np.arange(n)] = params["a1"]
+    A[1][np.arange(n), np.arange(n)] = -params["a2"]
+    for s in range(3):
+        A[s][0, params["drivers"][s]] += params["c"][s]
+    p = L + 1  # lags 0..L in the state
+    F = np.zeros((n * p, n * p))
+    for s in range(3):
+        F[:n, s * n:(s + 1) * n] = A[s]
+    F[n:, :-n] = np.eye(n * (p - 1))
+    Q = np.zeros((n * p, n * p))
+    Q[:n, :n] = np.eye(n)
+    S = solve_discrete_lyapunov(F, Q)
+
+    def idx(c):  # candidate index v*L + (l-1) -> state index
+        v, l = divmod(c, L)
+        return (l + 1) * n + v
+
+    def logdet(ix):
+        return np.linalg.slogdet(S[np.ix_(ix, ix)])[1] if ix else 0.0
+
+    def cmi(c, Z, target=0):
+        z = [idx(q) for q in Z]
+        x, y = idx(c), target
+        return 0.5 * (logdet([x] + z) + logdet([y] + z) - logdet(z) - logdet([x, y] + z))
+    return cmi
+
+
+def test_greedy_order_matches_exact_gaussian_cmi():
+    """Along the greedy path on the linear AR(2) network (N = 2,000, k = 4), every candidate's
+    KSG estimate lies within 0.05 nats of its exact Gaussian CMI given the path's conditioning
+    set (the estimator's bias and noise at this N stay below 0.045 here), and the greedy argmax
+    is the exact one wherever the exact gap between the best and second-best candidate exceeds
+    0.03 nats.  Dropping or misindexing a conditioning column, or a wrong sign, moves estimates
+    by more than that (e.g. I(x_0(t-1); y | x_2(t-1), x_0(t-2)) = 0.104 nats against 0.048
+    without the conditioning)."""
+    L, N = 5, 2000
+    net = workloads.ar2_network(seed=1, T=N + L, burn=1000)
+    cand, y = embed(net.data, target=0, max_lag=L)
+    exact = _var_exact_cmi(net.params, net.data.shape[1], L)
+    # the closed form itself: a candidate that is a lagged copy of Y given that lag is 0
+    assert abs(exact(0, [0])) < 1e-10
+    Z, checked = [], 0
+    for _ in range(5):
+        pool = [c for c in range(cand.shape[0]) if c not in Z]
+        est = [ksg_cmi(cand[c], y, cand[Z].T if Z else None, 4) for c in pool]
+        ex = np.array([exact(c, Z) for c in pool])
+        best = pool[int(np.argmax(est))]
+        order = np.argsort(ex)[::-1]
+        if ex[order[0]] - ex[order[1]] > 0.03:
+            assert best == pool[order[0]], (Z, best, pool[order[0]])
+            checked += 1
+        assert np.max(np.abs(np.array(est) - ex)) < 0.05
+        Z.append(best)
+    assert checked >= 2
