@@ -49,18 +49,19 @@ def _run(ctx, probs, out):
     return out.cpu().numpy().copy()
 
 
-@pytest.mark.parametrize("which", ["step", "mixed"])
+@pytest.mark.parametrize("which", ["step", "mixed", "step_alg2"])
 def test_graph_replay_matches_direct_and_oracle(lib, ctx, which):
     """Captured once, replayed three times with eager work and synchronisations in between:
     every replay equals the direct launches bit for bit (same kernels, same summation order)
-    and the oracle to 1e-12."""
+    and the oracle to 1e-12 (KSG algorithm 2: its own oracle)."""
     import torch
-    if which == "step":
+    if which.startswith("step"):
         probs, (p, cands, perms), keep = _step_batch(lib)
     else:
         probs, host, keep = _mixed_batch(lib)
     out = torch.empty(len(probs), dtype=torch.float64, device="cuda")
     ctx.set_option(ctx.OPT_CHECK_FINITE, 0)
+    ctx.set_option(ctx.OPT_ALGORITHM, 2 if which == "step_alg2" else 1)
     try:
         ctx.set_option(ctx.OPT_USE_GRAPH, 0)
         direct = _run(ctx, probs, out)
@@ -81,12 +82,15 @@ def test_graph_replay_matches_direct_and_oracle(lib, ctx, which):
     finally:
         ctx.set_option(ctx.OPT_USE_GRAPH, 0)
         ctx.set_option(ctx.OPT_CHECK_FINITE, 1)
-    if which == "step":
+        ctx.set_option(ctx.OPT_ALGORITHM, 1)
+    if which.startswith("step"):
+        from oracle.ksg2 import ksg2_cmi
+        est = ksg2_cmi if which == "step_alg2" else ksg_cmi
         n_perm = perms.shape[0]
         for idx in (0, 1, 2 * (n_perm + 1), len(probs) - 1):
             c, q = divmod(idx, n_perm + 1)
             x = cands[c] if q == 0 else cands[c][perms[q - 1]]
-            ref = ksg_cmi(x, p.y, p.z, 4)
+            ref = est(x, p.y, p.z, 4)
             assert abs(direct[idx] - ref) <= tol(ref), idx
     else:
         for i, (hp, k) in enumerate(zip(host, (4, 4, 8))):
