@@ -62,3 +62,13 @@ def test_noalloc_limits_and_nonfinite(lib, ctx):
     # the flag is cleared by the next call
     got, ref_api = _both(ctx, p, 4)
     assert abs(got - ref_api) <= tol(ref_api)
+
+
+def test_noalloc_at_the_size_limit(lib, ctx):
+    """N = KSG_NOALLOC_MAX_N rows and 16 columns (the largest call the static array holds),
+    then a small call: both equal the allocating entry point's estimate."""
+    big = workloads.random_problem(504, lib.KSG_NOALLOC_MAX_N, 1, 1, 14, 4)
+    small = workloads.random_problem(505, 500, 1, 2, 0, 4)
+    for p in (big, small):
+        got, ref_api = _both(ctx, p, 4)
+        assert abs(got - ref_api) <= tol(ref_api), (p.n, got, ref_api)
