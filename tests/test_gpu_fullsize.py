@@ -5,8 +5,8 @@ per process, about a minute each at N = 29,950).
 * the omnibus test of the 20-node logistic network's target 0 (501 problems of 16 columns at
   N = 29,950, key-ordered window search);
 * a greedy step of the same network with 14 conditioning columns (86 candidates x 501 rounds,
-  grouped, split over about ten launch chunks) and one with 22 (the grouped kernels compiled
-  for 15..30 columns);
+  grouped, split over about ten launch chunks) and ones with 22 and 30 (the grouped kernels
+  compiled for 15..30 columns; 30 is the widest a greedy step can condition on);
 * the 64-problem uneven batch, its three largest window-searched problems in full.
 """
 import multiprocessing as mp
@@ -73,7 +73,7 @@ def test_omnibus_shape_window_search(lib, ctx, logistic):
         assert abs(got[p] - ref) <= tol(ref), (p, got[p], ref)
 
 
-@pytest.mark.parametrize("m,n_perm", [(14, 500), (22, 100)])
+@pytest.mark.parametrize("m,n_perm", [(14, 500), (22, 100), (30, 50)])
 def test_logistic_greedy_step_grouped(lib, ctx, logistic, m, n_perm):
     cand, y, perms = logistic
     cond = _seeded_columns(m, 40 + m)
