@@ -120,8 +120,9 @@ typedef enum ksg_option {
                              * copies of its descriptors) and replay the graph when the same batch
                              * (same problems, columns, gathers, output and options) comes again,
                              * skipping the host planning, the upload and the per-launch overhead;
-                             * at most 32 graphs per context (least recently used dropped), retired
-                             * when a work buffer grows.  Used only with KSG_OPT_TIMING = 0 and
+                             * at most 32 graphs per context (least recently used dropped); the
+                             * graphs that write a work buffer are freed when it grows.  Used only
+                             * with KSG_OPT_TIMING = 0 and
                              * KSG_OPT_CHECK_FINITE = 0 (select_parents checks its data once and
                              * runs its steps without the check).  0 (default): direct launches */
   KSG_OPT_TIMING = 4,       /* 1: time every search-kernel launch with HIP events (default 0) */

@@ -896,6 +896,17 @@ int ksg_ctx::run_batch_graph(const std::vector<Problem>& probs, double* d_out) {
   BatchPlan P;
   int st = plan_batch(probs, P);
   if (st) return st;
+  // graphs captured before a work buffer was reallocated can never be replayed: free them now
+  bool stale = false;
+  for (const GraphEntry& g : graphs) stale |= g.gen != buf_gen;
+  if (stale) {
+    (void)hipStreamSynchronize(stream);
+    for (size_t i = graphs.size(); i-- > 0;)
+      if (graphs[i].gen != buf_gen) {
+        drop_graph(graphs[i]);
+        graphs.erase(graphs.begin() + i);
+      }
+  }
   if (graphs.size() >= kMaxGraphs) {  // evict the least recently used
     size_t lru = 0;
     for (size_t i = 1; i < graphs.size(); ++i)

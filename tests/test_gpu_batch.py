@@ -124,6 +124,33 @@ def test_graph_retired_when_work_buffers_grow(lib, ctx):
     assert ctx.graph_stats()["held"] == 0  # switching the option off drops the graphs
 
 
+def test_stale_graphs_are_freed(lib):
+    """On a fresh context: a small batch is captured, then a larger one grows the work buffers
+    (retiring the first graph, which is freed at once); the small batch then captures again,
+    and every result equals the direct launches."""
+    import torch
+    c = lib.Context(0)
+    try:
+        probs, _, keep = _step_batch(lib, n=700, n_cand=3, n_perm=5, seed=3)
+        big, _, keep2 = _step_batch(lib, n=6000, n_cand=8, n_perm=15, m=5, seed=4)
+        out = torch.empty(len(probs), dtype=torch.float64, device="cuda")
+        out_big = torch.empty(len(big), dtype=torch.float64, device="cuda")
+        c.set_option(c.OPT_CHECK_FINITE, 0)
+        c.set_option(c.OPT_USE_GRAPH, 1)
+        first = _run(c, probs, out)
+        assert c.graph_stats()["held"] == 1
+        got_big = _run(c, big, out_big)
+        assert c.graph_stats()["held"] == 1  # the small batch's graph was retired and freed
+        again = _run(c, probs, out)
+        st = c.graph_stats()
+        assert st["held"] == 2 and st["captures"] == 3 and st["replays"] == 0
+        c.set_option(c.OPT_USE_GRAPH, 0)
+        assert np.array_equal(first, _run(c, probs, out)) and np.array_equal(again, first)
+        assert np.array_equal(got_big, _run(c, big, out_big))
+    finally:
+        c.close()
+
+
 def test_select_parents_with_graphs(lib, ctx):
     """select_parents under KSG_OPT_USE_GRAPH gives the selection of the direct path."""
     net = workloads.ar2_network(seed=1, T=1205, burn=300)
