@@ -147,9 +147,8 @@ typedef enum ksg_option {
                              * usable */
   KSG_OPT_TILE_Q = 8,       /* queries per work-group of the brute-force kernels: 0 (default) =
                              * the autotuner's choice for the launch's size (256 before tuning),
-                             * or 64, 128, 256 forced, which also sets the tile of the window
-                             * search under algorithm 1 (256 otherwise); same results up to the
-                             * order of the FP64 sum */
+                             * or 64, 128, 256 forced; same results up to the order of the FP64
+                             * sum */
   KSG_OPT_WINDOWS = 6       /* 1 (default): single problems (not grouped) with k <= 4, N at or
                              * above the window threshold of their column count (2048 before
                              * ksg_autotune; the tuner's per-D choice after it; 2: 2048 always),

@@ -319,11 +319,6 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
     P.tile_q_plain = algorithm == 1 ? brute_tile_q(t_plain) : kTileQ;
     P.tile_q_wide = brute_tile_q(t_wide);
   }
-  // tile height of the window launches (one launch per column count): 256 queries, or the
-  // height KSG_OPT_TILE_Q fixes (algorithm 1).  Smaller tiles by launch size, as the
-  // brute-force launches take them, were measured no faster on the uneven batch: a smaller
-  // tile's phase 1 bounds its radii less tightly and its regroup has fewer queries to sort.
-  const int win_tq = algorithm == 1 && tile_q ? tile_q : kTileQ;
 
   // ---- per-problem descriptors (search of ungrouped problems + finalisation of all) ----
   std::vector<int> order;
@@ -366,8 +361,8 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
     d.dz = wide[i] ? kWideDims - dx - dy : p.dz;
     d.k = p.k;
     d.n_tiles = n_tiles_of(i);
-    if (group_of[i] < 0) {  // brute-force and window launches: their own tile height
-      const int tq = win_of[i] >= 0 ? win_tq : (wide[i] ? P.tile_q_wide : P.tile_q_plain);
+    if (group_of[i] < 0 && win_of[i] < 0) {  // brute-force launches: their own tile height
+      const int tq = wide[i] ? P.tile_q_wide : P.tile_q_plain;
       d.n_tiles = (int)((p.n + tq - 1) / tq);
     }
     d.eps_out = p.eps_out;
@@ -447,7 +442,7 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
       std::vector<WorkItem> seg = order_items(kv.second);
       double c = 0.0;
       for (const Unit& u : kv.second) c += u.cost;
-      P.wsegments.push_back(BatchPlan::Segment{kv.first, 5, (int)items.size(), (int)seg.size(), c, win_tq});
+      P.wsegments.push_back(BatchPlan::Segment{kv.first, 5, (int)items.size(), (int)seg.size(), c});
       items.insert(items.end(), seg.begin(), seg.end());
     }
   }
@@ -747,8 +742,7 @@ int ksg_ctx::enqueue_batch(const BatchPlan& P, const void* d_desc_v, const WorkI
         KSG_HIP(this, launch_ksg_alg2(d_desc, d_items + g.off, g.count, d_htab, d_part, g.D, g.kp, ls));
       } else if (L.kind == 1) {
         const BatchPlan::Segment& g = P.wsegments[L.seg];
-        KSG_HIP(this, launch_ksg_window(d_desc, d_items + g.off, g.count, d_htab, d_part, g.D, algorithm, d_w, ls,
-                                        g.tq));
+        KSG_HIP(this, launch_ksg_window(d_desc, d_items + g.off, g.count, d_htab, d_part, g.D, algorithm, d_w, ls));
       } else {
         KSG_HIP(this, launch_ksg_search(d_desc, d_items, P.n_plain_items, d_htab, d_part, P.common_shape, P.kp, ls,
                                         P.tile_q_plain));

@@ -140,8 +140,7 @@ hipError_t launch_ksg_search(const ProbDesc* d_desc, const WorkItem* d_items, in
 // items of problems that all have D columns (k <= 4), KSG algorithm alg (1 or 2).
 hipError_t launch_window_rank(const float* key, int n, int n_pad, int32_t* sigma, hipStream_t stream);
 hipError_t launch_ksg_window(const ProbDesc* d_desc, const WorkItem* d_items, int n_items, const double* d_htab,
-                             double* d_partials, int D, int alg, unsigned long long* d_work, hipStream_t stream,
-                             int tile_q = kTileQ);
+                             double* d_partials, int D, int alg, unsigned long long* d_work, hipStream_t stream);
 // KSG algorithm 2 over the work items of problems that all have D columns.
 hipError_t launch_ksg_alg2(const ProbDesc* d_desc, const WorkItem* d_items, int n_items,
                            const double* d_htab, double* d_partials, int D, int kp, hipStream_t stream);

@@ -54,11 +54,9 @@ hipError_t launch_window_rank(const float* key, int n, int n_pad, int32_t* sigma
 }
 
 hipError_t launch_ksg_window(const ProbDesc* d_desc, const WorkItem* d_items, int n_items, const double* d_htab,
-                             double* d_partials, int D, int alg, unsigned long long* d_work, hipStream_t stream,
-                             int tile_q) {
+                             double* d_partials, int D, int alg, unsigned long long* d_work, hipStream_t stream) {
   if (n_items <= 0) return hipSuccess;
   if (D < 2 || D > kMaxDimsCompiled || (alg != 1 && alg != 2)) return hipErrorInvalidValue;
-  if (tile_q != 64 && tile_q != 128 && tile_q != 256) return hipErrorInvalidValue;
   const ProbDesc* a0 = d_desc;
   const WorkItem* a1 = d_items;
   const double* a2 = d_htab;
@@ -66,7 +64,7 @@ hipError_t launch_ksg_window(const ProbDesc* d_desc, const WorkItem* d_items, in
   unsigned long long* a4 = d_work;
   void* args[] = {&a0, &a1, &a2, &a3, &a4};
   const void* kern = alg == 1 ? window_kernels_alg1[D - 2] : window_kernels_alg2[D - 2];
-  return hipLaunchKernel(kern, dim3(n_items), dim3(tile_q), args, 0, stream);
+  return hipLaunchKernel(kern, dim3(n_items), dim3(kTileQ), args, 0, stream);
 }
 
 }  // namespace ksg

@@ -7,9 +7,8 @@
 // The key is a column of Z: then d^Z >= |dkey| bounds all three counts (and the joint distance
 // bounds the radius), so rows outside the window can change neither.
 // Every distance is at least the key difference |fl(k_j - k_i)|, and that difference grows
-// monotonically with the distance of row j from row i in key order, so a tile of consecutive
-// rows (64, 128 or 256: the block size) first scans its own rows and then steps outward, right
-// and left; a
+// monotonically with the distance of row j from row i in key order, so a tile of 256
+// consecutive rows first scans its own rows and then steps outward, right and left; a
 // direction stops at the first step whose nearest key is, for every lane of the wave, at
 // least the lane's bound away (the current (k+1)-th distance in the radius pass, eps_i in the
 // count pass): no later row in that direction can change a result.  The estimate is a sum over
@@ -329,9 +328,7 @@ __global__ __launch_bounds__(kTileQ) void ksg_window_kernel(const ProbDesc* __re
   const int n_pad = pd->n_pad;
   const int k = pd->k;
   const int dx = pd->dx, dy = pd->dy;
-  // the tile height is the block size: 64, 128 or 256 queries (1, 2 or 4 waves)
-  const int TQ = (int)blockDim.x;
-  const int qraw = tile * TQ + (int)threadIdx.x;
+  const int qraw = tile * kTileQ + (int)threadIdx.x;
   bool valid = qraw < n;
   int qi = valid ? qraw : n - 1;
   cfptr col[D];
@@ -347,8 +344,8 @@ __global__ __launch_bounds__(kTileQ) void ksg_window_kernel(const ProbDesc* __re
   float qkey = keyc[qi];
   const int steps = n_pad / 4;
   // the tile's own rows (the last tile ends at the last real row's step)
-  const int s_lo = tile * (TQ / 4);
-  const int s_hi = min((tile + 1) * (TQ / 4), (n + 3) / 4) - 1;
+  const int s_lo = tile * (kTileQ / 4);
+  const int s_hi = min((tile + 1) * (kTileQ / 4), (n + 3) / 4) - 1;
   unsigned n1 = 0, n2 = 0;
 
   // ---- pass 1: (k+1) smallest joint distances within the key window ----
@@ -377,8 +374,8 @@ __global__ __launch_bounds__(kTileQ) void ksg_window_kernel(const ProbDesc* __re
     }
   };
   const int real_steps = (n + 3) / 4;
-  const int p_lo = max(s_lo - TQ / 4, 0);
-  const int p_hi = min(s_hi + TQ / 4, real_steps - 1);
+  const int p_lo = max(s_lo - kTileQ / 4, 0);
+  const int p_hi = min(s_hi + kTileQ / 4, real_steps - 1);
   for (int s = p_lo; s <= p_hi; ++s) radius_step(s);
   n1 += (unsigned)(p_hi - p_lo + 1);
 
@@ -387,9 +384,9 @@ __global__ __launch_bounds__(kTileQ) void ksg_window_kernel(const ProbDesc* __re
   auto regroup = [&](unsigned keybits) {
     s_ord[tid] = valid ? ((unsigned long long)keybits << 32) | (unsigned)qi : ~0ull;
     __syncthreads();
-    for (int size = 2; size <= TQ; size <<= 1) {
+    for (int size = 2; size <= kTileQ; size <<= 1) {
       for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        if (tid < TQ / 2) {
+        if (tid < kTileQ / 2) {
           const int lo = 2 * tid - (tid & (stride - 1));
           const int hi = lo + stride;
           const unsigned long long a = s_ord[lo], c = s_ord[hi];
@@ -414,7 +411,7 @@ __global__ __launch_bounds__(kTileQ) void ksg_window_kernel(const ProbDesc* __re
   };
   {
     const unsigned long long kk = regroup(__float_as_uint(b[KP - 1]));
-    const int src = kk != ~0ull ? (int)(unsigned)(kk & 0xffffffffu) - tile * TQ : tid;  // lane of the row
+    const int src = kk != ~0ull ? (int)(unsigned)(kk & 0xffffffffu) - tile * kTileQ : tid;  // lane of the row
 #pragma unroll
     for (int i = 0; i < KP; ++i) s_x[i][tid] = b[i];
     __syncthreads();
@@ -497,12 +494,7 @@ __global__ __launch_bounds__(kTileQ) void ksg_window_kernel(const ProbDesc* __re
     t = wave_sum(t);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = t;
     __syncthreads();
-    // fixed-order sum over the tile's 1, 2 or 4 waves
-    if (threadIdx.x == 0) {
-      const int nw = TQ >> 6;
-      partials[pd->part_base + tile] =
-          nw == 4 ? (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]) : (nw == 2 ? s_red[0] + s_red[1] : s_red[0]);
-    }
+    if (threadIdx.x == 0) partials[pd->part_base + tile] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
   }
 }
 

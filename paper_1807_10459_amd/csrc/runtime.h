@@ -50,8 +50,7 @@ struct Problem {
 struct BatchPlan {
   struct Segment {
     int D, kp, off, count;
-    double cost;            // brute-force operations of its problems (launch scheduling)
-    int tq = ksg::kTileQ;   // tile height of the launch (window segments)
+    double cost;  // brute-force operations of its problems (launch scheduling)
   };
   struct Chunk {
     std::array<int, 3> cls;       // m, G, KP

@@ -432,14 +432,12 @@ def test_device_props(lib):
         lib.device_props(10 ** 6)
 
 
-@pytest.mark.parametrize("tq", [0, 64, 128])
 @pytest.mark.parametrize("case", range(5))
-def test_window_search_matches_oracle(lib, ctx, case, tq):
+def test_window_search_matches_oracle(lib, ctx, case):
     """Single problems searched in key order with windows (N >= 2048, k <= 4, a Z column):
     every estimate equals the oracle's, and the brute-force search's up to the FP64 summation
     order.  Batches of multi-column X share Y and Z (as the omnibus test's do); single problems
-    of 1-D X are not grouped and take the same path; grid data put many rows on each key.
-    tq: the launches' tile height (0: the context's rule; 64 and 128 fixed)."""
+    of 1-D X are not grouped and take the same path; grid data put many rows on each key."""
     dims, kind, n_perm, k = [((3, 1, 2), "gaussian", 3, 4), ((1, 4, 3), "gaussian", 2, 3),
                              ((1, 1, 2), "gaussian", 0, 4), ((2, 1, 1), "grid", 2, 4),
                              ((1, 2, 5), "unit12", 1, 1)][case]
@@ -450,14 +448,10 @@ def test_window_search_matches_oracle(lib, ctx, case, tq):
     dp = dev(perms)
     probs = [lib.Problem(xd, yd, zd, k)] + [lib.Problem(xd, yd, zd, k, perm_x=dp[q]) for q in range(n_perm)]
     got = {}
-    ctx.set_option(ctx.OPT_TILE_Q, tq)
-    try:
-        for w in (1, 0):  # 2: windows from N = 2048 whatever an earlier autotune found
-            ctx.set_option(ctx.OPT_WINDOWS, 2 * w)
-            got[w] = ctx.cmi_batch(probs).cpu().numpy()
-    finally:
-        ctx.set_option(ctx.OPT_WINDOWS, 1)
-        ctx.set_option(ctx.OPT_TILE_Q, 0)
+    for w in (1, 0):  # 2: windows from N = 2048 whatever an earlier autotune found
+        ctx.set_option(ctx.OPT_WINDOWS, 2 * w)
+        got[w] = ctx.cmi_batch(probs).cpu().numpy()
+    ctx.set_option(ctx.OPT_WINDOWS, 1)
     assert np.max(np.abs(got[1] - got[0])) <= _sum_order_bound(n)
     for q in range(n_perm + 1):
         xs = p.x if q == 0 else p.x[perms[q - 1]]
@@ -487,9 +481,8 @@ def _degenerate_key_case(case):
     return p
 
 
-@pytest.mark.parametrize("tq", [0, 64])
 @pytest.mark.parametrize("case", range(4))
-def test_window_search_degenerate_keys(lib, ctx, case, tq):
+def test_window_search_degenerate_keys(lib, ctx, case):
     """Key-ordered windows on tied, far-out, signed-zero and denormal keys: estimates equal the
     oracle's and the brute-force search's (FP64 summation order aside); the window path runs
     (its operation count, over the pairs it visits, is at most the brute force's)."""
@@ -501,7 +494,6 @@ def test_window_search_degenerate_keys(lib, ctx, case, tq):
     probs = [lib.Problem(xd, yd, zd, p.k)] + [lib.Problem(xd, yd, zd, p.k, perm_x=dp[q]) for q in range(2)]
     got, ops = {}, {}
     ctx.set_option(ctx.OPT_TIMING, 1)
-    ctx.set_option(ctx.OPT_TILE_Q, tq)
     try:
         for w in (1, 0):  # 2: windows from N = 2048 whatever an earlier autotune found
             ctx.set_option(ctx.OPT_WINDOWS, 2 * w)
@@ -511,7 +503,6 @@ def test_window_search_degenerate_keys(lib, ctx, case, tq):
     finally:
         ctx.set_option(ctx.OPT_WINDOWS, 1)
         ctx.set_option(ctx.OPT_TIMING, 0)
-        ctx.set_option(ctx.OPT_TILE_Q, 0)
     brute = 3 * n * (n - 1) * (4 * (dx + dy + dz) + 2)
     assert ops[0] == pytest.approx(brute, rel=1e-12)
     assert 0 < ops[1] <= brute * 1.05, (ops[1], brute)
