@@ -743,8 +743,8 @@ def main():
                     help="also run a 1 GiB device-to-device copy (a known-size kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              "(the path shards by targets or work items with no collectives)",
+        print(f"bench.py times one GPU: the library runs on one device and has no collectives, so "
+              f"--gpus {args.gpus} is not supported (the path would shard by targets or by work items)",
               file=sys.stderr)
         sys.exit(2)
 

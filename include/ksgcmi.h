@@ -475,7 +475,7 @@ int ksg_maxstat_sequential(const double* table, int32_t rows, int32_t n_perm, do
 /* ---------------------------------------------------------------------------
  * Learned null: a 16-64-64-2 perceptron (ReLU hidden layers, BF16 parameters,
  * FP32 accumulation) predicting the step's tau_0.05 and tau_0.01 thresholds
- * scaled by sqrt(N).  The paper has no learned null; this is the build's gate
+ * scaled by sqrt(N).  The paper has no learned null; this is the library's own gate
  * in front of the surrogate test of the network-inference paragraph, which stays
  * as the fallback and the judge.
  *

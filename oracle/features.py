@@ -1,7 +1,8 @@
 """Feature vector of one greedy step for the learned-null gate, in FP64 (test infrastructure only).
 
-The paper gives no learned null; the 16 features are the build's reading of
-"(N, dims, k, sample moments, candidate CMI)".  All moments are population
+The paper gives no learned null; the 16 features are the library's own choice:
+the sample size, the dimensions, k, sample moments of the columns and the
+candidates' CMI values.  All moments are population
 moments of FP32 columns accumulated in FP64; CMI values are scaled by sqrt(N)
 so that they are O(1) across sample sizes.
 

@@ -5,7 +5,7 @@ a step's feature vector to its predicted surrogate max-statistic thresholds
 (tau_0.05 and tau_0.01, each scaled by sqrt(N)).  The paper does not describe
 a learned null (it only says that surrogate null distributions gate parent
 selection, Summary, network-inference paragraph); the network shape and the
-BF16-weights / FP32-accumulate arithmetic are the build's own choices.
+BF16-weights / FP32-accumulate arithmetic are the library's own choices.
 The oracle evaluates it in FP64 on the *same* BF16-rounded parameters that
 the device uses.
 
