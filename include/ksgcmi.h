@@ -152,7 +152,8 @@ typedef enum ksg_option {
   KSG_OPT_WINDOWS = 6       /* 1 (default): single problems (not grouped) with k <= 4, N at or
                              * above the window threshold of their column count (2048 before
                              * ksg_autotune; the tuner's per-D choice after it; 2: 2048 always),
-                             * no per-point outputs and an unpermuted Z column are searched with
+                             * an unpermuted Z column and, under algorithm 2, no per-point
+                             * outputs are searched with
                              * their rows in the order of that column, each tile scanning only the
                              * rows its radii, rectangle sides and counts can reach (same results
                              * up to the order of the FP64 sum; either KSG algorithm; under

@@ -149,8 +149,9 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
     }
   }
 
-  // ---- key-ordered windows: ungrouped problems (k <= 4, no per-point outputs, N large enough,
-  // at most 16 columns) that share an unpermuted Z column are searched in that column's order ----
+  // ---- key-ordered windows: ungrouped problems (k <= 4, N large enough, at most 16 columns;
+  // per-point outputs under algorithm 1 only) that share an unpermuted Z column are searched in
+  // that column's order ----
   std::vector<int> win_of(np, -1), win_key(np, -1);  // window set, key column (original index)
   P.wsets.clear();
   if (use_windows) {
@@ -160,7 +161,7 @@ int ksg_ctx::plan_batch(const std::vector<Problem>& probs, BatchPlan& P) {
       if (group_of[i] >= 0 || p.k + 1 > 5 || p.dz < 1 || p.dx + p.dy + p.dz > kMaxDimsCompiled ||
           p.n < window_min_n(p.dx + p.dy + p.dz))
         continue;
-      if (p.eps_out || p.counts_out || p.local_out) continue;
+      if ((p.eps_out || p.counts_out || p.local_out) && algorithm != 1) continue;
       int a_key = -1;
       for (int a = p.dx + p.dy; a < p.dx + p.dy + p.dz && a_key < 0; ++a)
         if (!p.perm[a]) a_key = a;

@@ -456,7 +456,11 @@ __global__ __launch_bounds__(kTileQ) void ksg_window_kernel(const ProbDesc* __re
                   open_r2, open_l2, n2);
     if (work && (threadIdx.x & 63) == 0)
       atomicAdd(&work[5], (unsigned long long)n1 * (unsigned)(2 * D) + (unsigned long long)n2 * (unsigned)(2 * D + 2));
-    tile_epilogue(pd, tile, qi, valid, eps, (int)acc[0], (int)acc[1], (int)acc[2], dx + dy == D, htab, partials,
+    // per-point outputs are indexed by the problem's own rows: row qi of the key order is row
+    // key_order[qi] of the problem
+    const bool outputs = pd->eps_out || pd->counts_out || pd->local_out;
+    const int orow = valid && outputs ? pd->key_order[qi] : qi;
+    tile_epilogue(pd, tile, orow, valid, eps, (int)acc[0], (int)acc[1], (int)acc[2], dx + dy == D, htab, partials,
                   s_red);
   } else {
     constexpr int T = KP - 1;  // >= k: ties kept at the k-th distance

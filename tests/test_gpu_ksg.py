@@ -517,6 +517,48 @@ def test_window_search_degenerate_keys(lib, ctx, case):
         assert abs(got[1][q] - ref) <= tol(ref), (case, q)
 
 
+_WINDOW_CASES = [((3, 1, 2), "gaussian", 4), ((1, 4, 3), "gaussian", 3), ((2, 1, 1), "grid", 4),
+                 ((1, 2, 5), "unit12", 1)]
+
+
+@pytest.mark.parametrize("case", range(len(_WINDOW_CASES) + 4))
+def test_window_search_per_point_outputs(lib, ctx, case):
+    """Per-point outputs on the key-ordered window path: eps, the three counts and the local
+    values of every row (written to the problem's own rows through the key order) equal the
+    oracle's bit for bit, with X permuted (a surrogate) and X/Y swapped shapes; the window path
+    ran (its operation count is below the brute force's, except where every key ties)."""
+    if case < len(_WINDOW_CASES):
+        dims, kind, k = _WINDOW_CASES[case]
+        n = 2300 + 61 * case
+        p = workloads.random_problem(1700 + case, n, *dims, k, kind=kind)
+        x, y, z = p.x, p.y, p.z
+    else:
+        p = _degenerate_key_case(case - len(_WINDOW_CASES))
+        n, dims, k = p.n, p.dims, p.k
+        x, y, z = p.x, p.y, p.z
+    perm = workloads.permutations(n, 1, seed=1800 + case)[0]
+    ctx.set_option(ctx.OPT_WINDOWS, 2)  # windows from N = 2048 whatever an earlier autotune found
+    ctx.set_option(ctx.OPT_TIMING, 1)
+    try:
+        ctx.take_timing()
+        eps, cnt, loc, cmi = _run(lib, ctx, x, y, z, k, perm=perm)
+        ops = ctx.take_timing()[2]
+    finally:
+        ctx.set_option(ctx.OPT_WINDOWS, 1)
+        ctx.set_option(ctx.OPT_TIMING, 0)
+    xs = x[perm]
+    e, a, b, c = ksg_counts(xs, y, z, k)
+    assert np.array_equal(eps, e) and np.array_equal(cnt[0], a), case
+    assert np.array_equal(cnt[1], b) and np.array_equal(cnt[2], c), case
+    ref = ksg_cmi_from_counts(n, k, a, b, c)
+    assert abs(cmi - ref) <= tol(ref), (case, cmi, ref)
+    assert np.allclose(loc, local_terms(n, k, a, b, c), rtol=0, atol=1e-13), case
+    brute = n * (n - 1) * (4 * sum(dims) + 2)
+    assert 0 < ops <= brute * 1.05, (ops, brute)
+    if case != len(_WINDOW_CASES):  # degenerate case 0: every key equal, no row excluded
+        assert ops < 0.9 * brute, (ops, brute)
+
+
 def test_uneven_batch_windows_match_brute_force(lib, ctx):
     """The 64-problem uneven batch without per-point outputs (so that the problems with k <= 4,
     N >= 2048 and a Z column take the key-ordered window search, in the launch configuration
