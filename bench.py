@@ -879,7 +879,7 @@ def main():
     dom = max(kernels, key=lambda kname: kern[kname][0])
     d_ms, d_ops, d_n = kern[dom]
     t_launch = d_ms / d_n * 1e-3
-    # Algorithmic operations of the method (brute force over ordered pairs, SURVEY 8(d) counts):
+    # Algorithmic operations of the method (brute force over ordered pairs):
     # radius 2D per pair, counts 2D + 2 per pair, for every problem of the step.
     pairs = N * (N - 1)
     brute_radius = sum((25 - m) * (N_PERM + 1) * pairs * 2 * (m + 2) for m in FORCED_M) * args.steps
