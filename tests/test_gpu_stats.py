@@ -269,6 +269,33 @@ def test_bench_configuration_sampled_parity(lib, ctx):
             assert abs(table[ci, p] - ref) <= tol(ref), (m, ci, p)
 
 
+def test_bench_configuration_grouped_equals_brute_force(lib, ctx):
+    """Every CMI of the timed workload (the AR(2) forced path, m = 1..8: 32,964 estimates at
+    N = 10,000) from the grouped kernels equals the brute-force single-problem kernel's (no
+    grouping, no windows), which the oracle pins elsewhere; the two differ only in the order of
+    the FP64 sum."""
+    net = workloads.ar2_network(seed=1)
+    L, P = 5, 200
+    perms = dev(workloads.permutations(10000, P, seed=11))
+    dcand, dy = ctx.embed(dev(net.data), target=0, max_lag=L)
+    first = [0, 1] + [src * L + (lag - 1) for (src, _, lag) in net.edges]
+    order = first + [c for c in range(25) if c not in first]
+    for m in range(1, 9):
+        cond = order[:m]
+        pool = [c for c in range(25) if c not in cond]
+        grouped, rg = ctx.greedy_step(dcand, dy, pool, cond, perms, k=4)
+        ctx.set_option(ctx.OPT_GROUP_SIZE, 0)
+        ctx.set_option(ctx.OPT_WINDOWS, 0)
+        try:
+            brute, rb = ctx.greedy_step(dcand, dy, pool, cond, perms, k=4)
+        finally:
+            ctx.set_option(ctx.OPT_GROUP_SIZE, -1)
+            ctx.set_option(ctx.OPT_WINDOWS, 1)
+        g, b = grouped.cpu().numpy(), brute.cpu().numpy()
+        assert np.all(np.abs(g - b) <= 1e-12 * np.maximum(np.abs(b), 1.0)), (m, float(np.max(np.abs(g - b))))
+        assert rg["c_star"] == rb["c_star"] and rg["count"] == rb["count"], m
+
+
 def test_select_parents_resume_from_record(lib, ctx):
     """A selection resumed from the first inclusions of an earlier run (its checkpoint) ends
     with the same parents; its new steps are the oracle's greedy steps from that set."""
