@@ -124,6 +124,8 @@ def kdtree_context(cand, y, perms, order, per_m=2):
 # the evaluation network (logistic seed 3).
 AR2_PLAN = [("ar2", 1000 + i, n) for i, n in enumerate([2000] * 30 + [5000] * 16 + [10000] * 8)]
 TRAIN_PLAN = AR2_PLAN + [("logistic", 2000 + i, t) for i, t in enumerate([1] * 40 + [2] * 12 + [5] * 8 + [10] * 6)]
+# more paths of the evaluation's size class (10 trials, N = 29,950), whose selections run deepest
+DEEP_PLAN = [("logistic", 2066 + i, 10) for i in range(6)]
 
 
 def _subsets_for(g):
@@ -280,9 +282,13 @@ def c4_evaluate(ctx, args, log):
     import workloads
     from paper_1807_10459_amd.learned_null import calibrate, train_threshold_net
     t0 = time.perf_counter()
-    if args.dataset:  # a training set written earlier by --dump-dataset (same recipe)
-        d = np.load(args.dataset)
-        feats, targ, obs, net_id = (torch.from_numpy(d[k]).cuda() for k in ("feats", "targ", "obs", "net_id"))
+    if args.dataset:  # training sets written earlier by --dump-dataset (same recipes), concatenated
+        parts, off = [], 0
+        for path in args.dataset:
+            d = np.load(path)
+            parts.append([d["feats"], d["targ"], d["obs"], d["net_id"] + off])
+            off = int(parts[-1][3].max()) + 1  # network ids stay distinct across the files
+        feats, targ, obs, net_id = (torch.from_numpy(np.concatenate([q[i] for q in parts])).cuda() for i in range(4))
     else:
         feats, targ, obs, net_id = c4_dataset(ctx, TRAIN_PLAN, log=log)
     t_data = time.perf_counter() - t0
@@ -724,7 +730,11 @@ def main():
     ap.add_argument("--workload", default="ar2", choices=["ar2", "c4", "modes", "omnibus", "uneven"],
                     help="ar2: CMI/s on the AR(2) forced path (default); c4: learned vs plain null")
     ap.add_argument("--targets", default=None, help="c4: comma-separated targets (default all 20)")
-    ap.add_argument("--dataset", default=None, help="c4: load the training set from this npz")
+    ap.add_argument("--dataset", nargs="+", default=None,
+                    help="c4: load the training set from these npz files (concatenated)")
+    ap.add_argument("--plan", default="train", choices=["train", "deep"],
+                    help="--dump-dataset: the training networks (train), or six more of the evaluation's "
+                         "size class (deep)")
     ap.add_argument("--include-rate", type=float, default=None,
                     help="c4: calibrate the gate with this allowance of wrong inclusions (and rate/2 of wrong "
                          "stops) instead of rate/2 on both sides")
@@ -803,7 +813,8 @@ def main():
 
     if args.dump_dataset:
         ctx = ksg.Context(0)
-        f, t, o, nid = c4_dataset(ctx, TRAIN_PLAN, log=lambda m: print(m, file=sys.stderr, flush=True))
+        f, t, o, nid = c4_dataset(ctx, TRAIN_PLAN if args.plan == "train" else DEEP_PLAN,
+                                  log=lambda m: print(m, file=sys.stderr, flush=True))
         np.savez_compressed(args.dump_dataset, feats=f.cpu().numpy(), targ=t.cpu().numpy(),
                             obs=o.cpu().numpy(), net_id=nid.cpu().numpy())
         print(json.dumps({"dataset": args.dump_dataset, "examples": int(f.shape[0])}))
