@@ -294,6 +294,14 @@ def c4_evaluate(ctx, args, log):
     t_data = time.perf_counter() - t0
     held = (net_id % 7) == 3
     tr = torch.nonzero(~held).flatten()
+    if args.real_weight > 1:
+        # the full-pool example of every step (the first of its step's examples: the steps of a
+        # path come in order, each with the full pool and 127 subsets) repeated real_weight times
+        nid = net_id.cpu().numpy()
+        first_row = np.r_[0, np.nonzero(np.diff(nid))[0] + 1]
+        row_in_path = np.arange(nid.size) - np.repeat(first_row, np.diff(np.r_[first_row, nid.size]))
+        real = torch.from_numpy(row_in_path % 128 == 0).cuda()
+        tr = torch.cat([tr] + [tr[real[tr]]] * (args.real_weight - 1))
     order = torch.from_numpy(workloads.permutations(tr.numel(), 1, seed=4242)[0].astype(np.int64)).cuda()
     tr = tr[order]
     t1 = time.perf_counter()
@@ -735,6 +743,8 @@ def main():
     ap.add_argument("--plan", default="train", choices=["train", "deep"],
                     help="--dump-dataset: the training networks (train), or six more of the evaluation's "
                          "size class (deep)")
+    ap.add_argument("--real-weight", type=int, default=1,
+                    help="c4: repeat each step's full-pool training example this many times")
     ap.add_argument("--include-rate", type=float, default=None,
                     help="c4: calibrate the gate with this allowance of wrong inclusions (and rate/2 of wrong "
                          "stops) instead of rate/2 on both sides")
