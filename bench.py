@@ -313,6 +313,13 @@ def c4_evaluate(ctx, args, log):
     hi_idx = torch.nonzero(held & (feats[:, 0] >= float(np.log(14000.0)))).flatten()
     cal = calibrate(net, feats[hi_idx].contiguous(), obs[hi_idx].contiguous(), rate=0.0025,
                     include_rate=args.include_rate)
+    deep = None
+    if args.deep_dz > 0:  # margins of their own for the deep steps (feature 3 is d_z)
+        dp_idx = torch.nonzero(held & (feats[:, 0] >= float(np.log(14000.0))) & (feats[:, 3] >= args.deep_dz)).flatten()
+        cal_d = calibrate(net, feats[dp_idx].contiguous(), obs[dp_idx].contiguous(), rate=0.0025,
+                          include_rate=args.include_rate)
+        deep = (args.deep_dz, cal_d["margin_lo"], cal_d["margin_hi"])
+        log(f"deep-step calibration (d_z >= {args.deep_dz}, {dp_idx.numel()} examples): {cal_d}")
     log(f"dataset {feats.shape[0]} examples in {t_data:.1f} s; training {t_train:.1f} s "
         f"(loss {hist[0]:.4f} -> {hist[-1]:.4f}); calibration {cal}")
 
@@ -343,7 +350,7 @@ def c4_evaluate(ctx, args, log):
             kw = dict(k=K, max_lag=MAX_LAG, alpha=0.05, omnibus=True)
             if mode != "plain":
                 kw.update(learned=net, margin_lo=cal["margin_lo"], margin_hi=cal["margin_hi"], judge=mode == "judged",
-                          verify_stop=True)
+                          verify_stop=True, deep_margins=deep)
             out[t] = ctx.select_parents(data, t, perms, **kw)
             log(f"{mode} target {t}: parents {out[t]['parents']} steps {out[t]['n_steps']} "
                 f"truncated {out[t]['truncated']} fallback {out[t]['n_fallback']} disagree {out[t]['n_disagree']} "
@@ -411,6 +418,8 @@ def c4_evaluate(ctx, args, log):
                                     else sum(r["truncated_targets_plain"] for r in recs)),
         "plain_from": args.plain_json,
         "include_rate": args.include_rate,
+        "deep_margins": deep,
+        "real_weight": args.real_weight,
         "omnibus": {str(t): [r["omnibus_tested"], r["omnibus_significant"]] for t, r in learned.items()},
         "truncated_targets_learned": sum(int(r["truncated"]) for r in learned.values()),
         "parents_plain": {str(t): r["parents"] for t, r in plain.items()},
@@ -743,6 +752,9 @@ def main():
     ap.add_argument("--plan", default="train", choices=["train", "deep"],
                     help="--dump-dataset: the training networks (train), or six more of the evaluation's "
                          "size class (deep)")
+    ap.add_argument("--deep-dz", type=int, default=0,
+                    help="c4: steps conditioning on at least this many columns use margins calibrated on "
+                         "the held-out examples of that depth")
     ap.add_argument("--real-weight", type=int, default=1,
                     help="c4: repeat each step's full-pool training example this many times")
     ap.add_argument("--include-rate", type=float, default=None,

@@ -403,6 +403,12 @@ typedef struct ksg_select_opts {
   int32_t verify_stop; /* learned null: 1 = a step the gate would stop on runs the plain test,
                         * whose decision is taken (a wrong stop loses every later parent, a wrong
                         * inclusion adds one); 0 = the gate decides both ways */
+  int32_t deep_dz;     /* learned null: 0 = margin_lo/margin_hi on every step; > 0 = steps that
+                        * condition on at least deep_dz columns use margin_lo_deep/margin_hi_deep
+                        * (the thresholds' spread narrows with depth while the network's error
+                        * does not, so deep steps need margins of their own) */
+  double margin_lo_deep;
+  double margin_hi_deep;
 } ksg_select_opts;
 
 enum { KSG_MODE_MULTIVARIATE_TE = 0, KSG_MODE_BIVARIATE_TE = 1, KSG_MODE_MULTIVARIATE_MI = 2 };

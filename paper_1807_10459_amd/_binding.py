@@ -54,7 +54,8 @@ class _SelectOpts(C.Structure):
                 ("learned", C.c_void_p), ("margin_lo", C.c_double), ("margin_hi", C.c_double),
                 ("judge", C.c_int32), ("max_steps", C.c_int32), ("mode", C.c_int32), ("prune", C.c_int32),
                 ("sequential", C.c_int32), ("max_cond", C.c_int32), ("resume", C.c_void_p),
-                ("n_resume", C.c_int32), ("verify_stop", C.c_int32)]
+                ("n_resume", C.c_int32), ("verify_stop", C.c_int32), ("deep_dz", C.c_int32),
+                ("margin_lo_deep", C.c_double), ("margin_hi_deep", C.c_double)]
 
 
 class _ParentSet(C.Structure):
@@ -404,13 +405,16 @@ class Context:
                        margin_lo: float = 1.0, margin_hi: float = 1.0, judge: bool = False,
                        max_steps: int = 0, capacity: int = 64, mode: str = "mte",
                        prune: bool = False, sequential: bool = False, max_cond: int = 0,
-                       resume: Sequence[int] = (), verify_stop: bool = False) -> dict:
+                       resume: Sequence[int] = (), verify_stop: bool = False,
+                       deep_margins: tuple | None = None) -> dict:
         """Parents of one target.  mode: "mte" (multivariate TE), "bte" (bivariate TE) or "mmi"
         (multivariate MI); prune: min-statistic pruning of the selected sources; sequential:
         sequential max-statistic test of the kept sources; max_cond: conditioning columns allowed
         (0 = the library's limit); "truncated" in the result reports a selection that ended at it;
         resume: candidate indices an earlier run included (in order), to continue from them;
-        verify_stop: with a learned null, a step the gate would stop on runs the plain test."""
+        verify_stop: with a learned null, a step the gate would stop on runs the plain test;
+        deep_margins: (deep_dz, margin_lo, margin_hi) for the steps that condition on at least
+        deep_dz columns."""
         import torch
         _check_dtype(data, torch.float32, "data")
         _check_dtype(perms, torch.int32, "perms")
@@ -420,6 +424,9 @@ class Context:
                            float(margin_hi), int(bool(judge)), int(max_steps), MODES[mode], int(bool(prune)),
                            int(bool(sequential)), int(max_cond))
         opts.verify_stop = int(bool(verify_stop))
+        if deep_margins is not None:
+            opts.deep_dz, opts.margin_lo_deep, opts.margin_hi_deep = (int(deep_margins[0]), float(deep_margins[1]),
+                                                                      float(deep_margins[2]))
         res_arr = np.ascontiguousarray(np.asarray(list(resume), dtype=np.int32))
         if res_arr.size:
             opts.resume, opts.n_resume = res_arr.ctypes.data, int(res_arr.size)

@@ -83,6 +83,8 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
     return c->fail(KSG_EINVAL, "select_parents: resume needs n_resume >= 0, a host array, and a multivariate mode");
   if (o->learned && !(o->margin_lo >= 0 && o->margin_hi >= 0))
     return c->fail(KSG_EINVAL, "select_parents: margins must be >= 0");
+  if (o->learned && o->deep_dz != 0 && !(o->deep_dz > 0 && o->margin_lo_deep >= 0 && o->margin_hi_deep >= 0))
+    return c->fail(KSG_EINVAL, "select_parents: deep_dz must be >= 0 and the deep margins >= 0");
   if (o->mode < KSG_MODE_MULTIVARIATE_TE || o->mode > KSG_MODE_MULTIVARIATE_MI || (o->prune != 0 && o->prune != 1) ||
       (o->sequential != 0 && o->sequential != 1))
     return c->fail(KSG_EINVAL, "select_parents: mode %d / prune %d / sequential %d not known", o->mode, o->prune,
@@ -182,8 +184,10 @@ extern "C" int select_parents(ksg_ctx* c, const float* data, int32_t n_vars, int
       if (st) return st;
       out->n_cmi += cands;
       int verdict = 0;
+      const bool deep = o->deep_dz > 0 && (int)s.selected.size() >= o->deep_dz;
       st = gate.decide(c, d_cmi, cands, s.P + 1, s.pool, 1, 1, (int)s.selected.size(), o->k, s.P,
-                       o->margin_lo, o->margin_hi, &verdict, &c_star, &t_obs, pred);
+                       deep ? o->margin_lo_deep : o->margin_lo, deep ? o->margin_hi_deep : o->margin_hi, &verdict,
+                       &c_star, &t_obs, pred);
       if (st) return st;
       gate_verdict = verdict;
       if (verdict > 0 || (verdict < 0 && !o->verify_stop)) {

@@ -233,3 +233,20 @@ def test_verify_stop_confirms_every_predicted_stop(lib, ctx):
         assert raw["parents"] == plain["parents"][:first]
     else:
         assert raw["parents"] == plain["parents"]
+
+
+def test_deep_step_margins(lib, ctx):
+    """With deep_dz = 1 the first step (no conditioning) uses margin_lo/margin_hi and every later
+    step the deep pair: huge shallow margins leave step 0 to the surrogates, zero deep margins let
+    the gate decide every later step; negative deep_dz is rejected."""
+    net = lib.ThresholdNet(ctx, workloads.mlp_init(22))
+    data = workloads.logistic_network(seed=996, n_trials=1, T=3000).data
+    perms = dev(workloads.permutations(2995, 99, seed=995))
+    r = ctx.select_parents(dev(data), 5, perms, k=4, max_lag=5, learned=net, margin_lo=1e30, margin_hi=1e30,
+                           deep_margins=(1, 0.0, 0.0), max_steps=6)
+    v = [st["verdict"] for st in r["steps"]]
+    assert v[0] == 0 and r["n_fallback"] >= 1
+    assert all(x in (-1, 1) for x in v[1:]), v
+    assert r["n_gate_decided"] == r["n_steps"] - 1
+    with pytest.raises(lib.KsgError):
+        ctx.select_parents(dev(data), 5, perms, k=4, max_lag=5, learned=net, deep_margins=(-1, 0.0, 0.0))
