@@ -580,6 +580,7 @@ def _host_cpu():
             return None
     sockets, cores_per, threads = num("Socket(s)"), num("Core(s) per socket"), num("CPU(s)")
     return {"model": info.get("Model name", _cpu_model()), "sockets": sockets,
+            "family_model_stepping": [info.get("CPU family"), info.get("Model"), info.get("Stepping")],
             "physical_cores": sockets * cores_per if sockets and cores_per else None,
             "hardware_threads": threads, "threads_usable": os.cpu_count()}
 
