@@ -16,7 +16,8 @@
 // the same columns, a benchmark step) the graph is replayed and the host planning, the upload
 // and the per-launch overhead are skipped.  The graph owns private copies of the descriptors,
 // items and pack jobs; the work buffers it writes (pool, E, T, partials) are the context's and
-// are rewritten by every replay, and any reallocation of them retires every graph.
+// are rewritten by every replay, and a reallocation of any of them retires every graph
+// captured before it (freed at the next capture).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
